@@ -1,0 +1,68 @@
+/*
+ * md_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow CPU reference for mixed-datatype matrix multiplication
+ *     C := beta*C + alpha*op(A)*op(B)
+ * as stated in Van Zee, Parikh, van de Geijn, "Supporting mixed-datatype matrix
+ * multiplication within the BLIS framework" (Section 1 for the operation and the
+ * op() variants; Section 3.2 / Figure "mixeddom" for the eight domain cases;
+ * Section 4 for precision; Section 6 for the scalar policies).
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+ * call this.  It shares no code, header, table or helper with the GPU library.
+ *
+ * Storage tags: 0 = s (float), 1 = d (double), 2 = c (float complex,
+ * interleaved re,im), 3 = z (double complex, interleaved).  Matrices are
+ * column-major; a leading dimension counts elements of the operand's own type.
+ */
+#ifndef MD_ORACLE_H
+#define MD_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_ERR_ALPHA_IMAG 1   /* Section 6.2: Im(alpha) != 0 in cases 1a,1b,1c,2ab,2ac,2bc */
+#define ORACLE_ERR_ARG (-1)       /* malformed arguments (trans letter, dims, tags, ld) */
+
+/* Domain case of Figure "mixeddom", encoded 0..7 as
+ * 0:"0" 1:"1b" 2:"1a" 3:"2ab" 4:"1c" 5:"2bc" 6:"2ac" 7:"3"
+ * (the figure's row order). */
+int md_oracle_case(int dtc, int dta, int dtb);
+
+/* Minimum flop count of the case, Figure "mixeddom": 2mnk, 4mnk or 8mnk. */
+double md_oracle_flops(int dtc, int dta, int dtb, int64_t m, int64_t n, int64_t k);
+
+/*
+ * Full reference.  Writes, for every 0<=i<m, 0<=j<n,
+ *   cref[2*(i+j*m)], cref[2*(i+j*m)+1] : the exact-input FP64 result (re, im);
+ *                                         im is 0 when C is real-stored
+ *   g[i+j*m] (if g != NULL)            : sum_p |op(A)_ip| * |op(B)_pj|
+ *                                         (complex modulus), the bound term.
+ * C itself is read, never written.  Returns ORACLE_OK, ORACLE_ERR_ALPHA_IMAG
+ * (cref untouched) or ORACLE_ERR_ARG.
+ */
+int md_oracle_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                   double alpha_re, double alpha_im,
+                   const void *A, int dta, int64_t lda,
+                   const void *B, int dtb, int64_t ldb,
+                   double beta_re, double beta_im,
+                   const void *C, int dtc, int64_t ldc,
+                   double *cref, double *g);
+
+/* The same definition evaluated only at `count` entries (rows[t], cols[t]);
+ * cref has 2*count doubles, g (optional) count doubles. */
+int md_oracle_gemm_at(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                      double alpha_re, double alpha_im,
+                      const void *A, int dta, int64_t lda,
+                      const void *B, int dtb, int64_t ldb,
+                      double beta_re, double beta_im,
+                      const void *C, int dtc, int64_t ldc,
+                      int64_t count, const int64_t *rows, const int64_t *cols,
+                      double *cref, double *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,49 @@
+"""Plausible mistakes planted in copies of the oracle (on the CPU) must each be
+caught by at least one pin.  This shows the pins constrain every part of the
+definition: sign and index of each term, transposition, conjugation, the
+scalar policies and the real-C projection."""
+import os
+import shutil
+
+import pytest
+
+import oracle
+import oracle_pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "md_oracle.c")
+
+MUTANTS = {
+    "re_sign": ("sr += ar * br - ai * bi;", "sr += ar * br + ai * bi;"),
+    "im_sign": ("si += ar * bi + ai * br;", "si += ar * bi - ai * br;"),
+    "im_term_dropped": ("si += ar * bi + ai * br;", "si += ar * bi;"),
+    "no_conj": ("*im = -*im;", "(void)0;"),
+    "trans_ignored": ("fetch(X, dt, ld, p, i, re, im);", "fetch(X, dt, ld, i, p, re, im);"),
+    "index_transposed": ("int64_t idx = r + c * ld;", "int64_t idx = r * ld + c;"),
+    "alpha_cross_sign": ("double tr = use_ab ? alpha_re * sr - alpha_im * si : 0.0;",
+                         "double tr = use_ab ? alpha_re * sr + alpha_im * si : 0.0;"),
+    "beta_imag_kept_for_real_c": ("double bim = tag_complex(dtc) ? beta_im : 0.0;",
+                                  "double bim = beta_im;"),
+    "real_c_keeps_imag": ("*out_im = tag_complex(dtc) ? ri : 0.0;", "*out_im = ri;"),
+    "alpha_rule_case0": ("return alpha_im != 0.0 && cs != 0 && cs != 7;",
+                         "return alpha_im != 0.0 && cs != 7;"),
+    "beta_conj": ("rr = bre * cr - bim * ci + tr;", "rr = bre * cr + bim * ci + tr;"),
+    "c_read_when_beta_zero": ("if (bre != 0.0 || bim != 0.0) {", "if (1) {"),
+    "single_promoted_wrong": ("*im = (double)((const float *)X)[2 * idx + 1];",
+                              "*im = (double)((const float *)X)[2 * idx];"),
+    "last_k_dropped": ("for (int64_t p = 0; p < k; ++p) {", "for (int64_t p = 0; p + 1 < k; ++p) {"),
+    "flops_case2": ("double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 4.0 : 8.0);",
+                    "double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 8.0 : 8.0);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor not found: " + old
+    shutil.copy(os.path.join(os.path.dirname(SRC), "md_oracle.h"), tmp_path / "md_oracle.h")
+    (tmp_path / "mut.c").write_text(src.replace(old, new))
+    lib = oracle.build(str(tmp_path / "mut.c"), str(tmp_path / "libmut.so"))
+    res = oracle_pins.run_all(oracle.Oracle(lib))
+    caught = [k for k, v in res.items() if v]
+    assert caught, "mutant %s passed every pin" % name
