@@ -1,0 +1,176 @@
+/*
+ * mdgemm.h -- mixed-datatype general matrix multiplication on MI355X (gfx950).
+ *
+ *     C := beta*C + alpha*op(A)*op(B)
+ *
+ * where each of A, B and C is independently stored as single or double
+ * precision, real or complex (s, d, c, z) and the computation precision is
+ * chosen separately from the storage precisions.  The operation and the three
+ * op() variants are those of the BLAS gemm (Van Zee, Parikh, van de Geijn,
+ * "Supporting mixed-datatype matrix multiplication within the BLIS framework",
+ * Section 1); the domain of the computation follows from which operands are
+ * complex (Section 3.2, Figure "mixeddom"); the computation precision and the
+ * target types of A and B follow Section 4.1; the scalar policies follow
+ * Section 6.
+ *
+ * Storage conventions (all entry points):
+ *   - matrices are column-major; complex elements are interleaved (re, im);
+ *   - a leading dimension counts elements of that operand's own type and must
+ *     be >= max(1, rows) of the stored matrix (rows of A are m for transa 'N',
+ *     else k; rows of B are k for transb 'N', else n; rows of C are m);
+ *   - A, B and C are device pointers owned by the caller; A and B are only
+ *     read; C is updated in place and must not overlap A or B (A may equal B);
+ *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     the call returns before it completes: the caller keeps every buffer alive
+ *     until the stream has finished;
+ *   - on any error return nothing is enqueued and C is unmodified.
+ *
+ * Return codes: 0 on success; -i when argument i (1-based, in mdgemm's order)
+ * is invalid; positive MD_ERR_* codes otherwise (see mdgemm_strerror).
+ */
+#ifndef MDGEMM_H
+#define MDGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage type of one operand (domain x precision, Section 1's s/d/c/z). */
+typedef enum { MD_S = 0, MD_D = 1, MD_C = 2, MD_Z = 3 } md_dt;
+
+/* Computation precision (Section 4.1.1).  MD_COMP_DEFAULT selects the storage
+ * precision of C.  MD_COMP_S_BF16X3 has single-precision semantics but forms
+ * each real product from bfloat16 halves (hi*hi + hi*lo + lo*hi) on the
+ * bf16 matrix cores with FP32 accumulation; it is an addition of this
+ * library, not of the paper. */
+typedef enum {
+    MD_COMP_DEFAULT = -1,
+    MD_COMP_S = 0,
+    MD_COMP_D = 1,
+    MD_COMP_S_BF16X3 = 2
+} md_comp;
+
+/* alpha and beta are always passed as complex double; see Section 6 for how
+ * each case uses them. */
+typedef struct { double re, im; } md_scalar;
+
+/* Domain cases of Figure "mixeddom" (C, A, B domains). */
+typedef enum {
+    MD_CASE_0 = 0,   /* R R R : C += AB                       2mnk */
+    MD_CASE_1A = 1,  /* R C R : C += Re(A) B                  2mnk */
+    MD_CASE_1B = 2,  /* R R C : C += A Re(B)                  2mnk */
+    MD_CASE_1C = 3,  /* C R R : Re(C) += AB                   2mnk */
+    MD_CASE_2AB = 4, /* R C C : C += Re(AB)                   4mnk */
+    MD_CASE_2AC = 5, /* C C R : C += AB, Im(B) = 0 skipped    4mnk */
+    MD_CASE_2BC = 6, /* C R C : C += AB, Im(A) = 0 skipped    4mnk */
+    MD_CASE_3 = 7    /* C C C : C += AB                       8mnk */
+} md_case;
+
+/* Status codes. */
+#define MD_OK 0
+#define MD_ERR_ALPHA_IMAG 1  /* Im(alpha) != 0 in case 1a, 1b, 1c, 2ab, 2ac or 2bc (Section 6.2) */
+#define MD_ERR_HIP 2         /* HIP launch or runtime failure */
+#define MD_ERR_BUDGET 3      /* a serving request exceeds the memory budget */
+#define MD_ERR_STATE 4       /* call not valid in the object's current state */
+#define MD_ERR_UNSUPPORTED 5 /* valid request that this build cannot run */
+
+/*
+ * mdgemm -- one mixed-datatype product.
+ *
+ * Arguments (position in parentheses is the one reported as -i on error):
+ *  (1) transa, (2) transb : 'N', 'T' or 'C' (lower case accepted); 'C' on a
+ *        real operand equals 'T'.
+ *  (3) m, (4) n, (5) k     : op(A) is m x k, op(B) is k x n, C is m x n; >= 0.
+ *  (6) alpha               : cast to the computation precision (Section 6.1,
+ *        option 1).  Im(alpha) is ignored in case 0 and used in case 3; in the
+ *        other six cases a non-zero Im(alpha) returns MD_ERR_ALPHA_IMAG.
+ *  (7) A, (8) dta, (9) lda : operand A, its storage type, leading dimension.
+ *  (10) B, (11) dtb, (12) ldb : operand B likewise.
+ *  (13) beta               : cast to C's storage precision (Section 6.1,
+ *        option 1); Im(beta) is ignored when C is real.  beta == 0 means C is
+ *        not read (NaN in C does not propagate).
+ *  (14) C, (15) dtc, (16) ldc : operand C likewise; updated in place.
+ *  (17) comp               : computation precision (md_comp).
+ *  (18) stream             : hipStream_t to enqueue on.
+ *
+ * The result is beta*C + alpha*op(A)*op(B) computed with the product in the
+ * computation precision and the update in the wider of the computation and C
+ * precisions, rounded once to C's storage type.  m == 0 or n == 0 is a
+ * no-op; alpha == 0 or k == 0 only scales C by beta (A and B are not read).
+ */
+int mdgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+           md_scalar alpha,
+           const void *A, md_dt dta, int64_t lda,
+           const void *B, md_dt dtb, int64_t ldb,
+           md_scalar beta,
+           void *C, md_dt dtc, int64_t ldc,
+           md_comp comp, void *stream);
+
+/* What mdgemm would do with the same arguments, computed on the host only
+ * (no device call, usable without a GPU). */
+typedef struct {
+    int status;        /* the value mdgemm would return */
+    int domain_case;   /* md_case */
+    int comp;          /* resolved computation precision (MD_COMP_S/D/S_BF16X3) */
+    int quick;         /* 0: full product; 1: nothing to do; 2: C := beta*C only */
+    double flops;      /* algorithmic flops of Figure "mixeddom" (0 if quick) */
+    int64_t m_real;    /* rows of the real product the case is lowered to */
+    int64_t n_real;    /* columns of that real product */
+    int64_t k_real;    /* inner dimension of that real product */
+    int a_parts;       /* parts of A that reach C: 1 = real or Re only, 2 = Re and Im */
+    int b_parts;       /* parts of B that reach C */
+    int tile_m, tile_n, tile_k; /* workgroup tile of the real product */
+    int64_t workgroups;         /* workgroups launched */
+    char kernel[48];            /* kernel variant name */
+} md_plan;
+
+int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                md_scalar alpha,
+                const void *A, md_dt dta, int64_t lda,
+                const void *B, md_dt dtb, int64_t ldb,
+                md_scalar beta,
+                void *C, md_dt dtc, int64_t ldc,
+                md_comp comp, md_plan *out);
+
+/*
+ * Grouped form: `count` independent products enqueued as ONE persistent
+ * kernel launch on `stream`.  Each descriptor holds exactly mdgemm's
+ * arguments (1)-(17); products may differ in shape, storage types and
+ * computation precision.  Every descriptor is validated first; if any is
+ * invalid the call returns -(1000*index + i) for the first bad argument i of
+ * descriptor `index` (or MD_ERR_ALPHA_IMAG) and enqueues nothing.  The C
+ * operands must be pairwise disjoint.  The library keeps an internal device
+ * work table that it grows as needed; calls on one device are serialised
+ * internally up to the enqueue.
+ */
+typedef struct {
+    char transa, transb;
+    int64_t m, n, k;
+    md_scalar alpha;
+    const void *A; md_dt dta; int64_t lda;
+    const void *B; md_dt dtb; int64_t ldb;
+    md_scalar beta;
+    void *C; md_dt dtc; int64_t ldc;
+    md_comp comp;
+} md_gemm_desc;
+
+int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream);
+
+/* Tile table used for the grouped kernel's work decomposition and the plain
+ * path's tile choice: load one written by the autotuner (a small text file,
+ * see the autotuner's documentation), or reset to the built-in defaults with
+ * path == NULL.  Returns 0 or MD_ERR_STATE if the file is malformed. */
+int mdgemm_tune_load(const char *path);
+
+/* Human-readable text for a status code. */
+const char *mdgemm_strerror(int status);
+
+/* Library version string. */
+const char *mdgemm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,78 @@
+// md_internal.h -- shared between the host planner and the device kernels of
+// libmdgemm (never installed, never seen by callers).
+#pragma once
+#include <stdint.h>
+
+#include "../../include/mdgemm.h"
+
+namespace md {
+
+// Lowering of a domain case onto one real product (Figure "mixeddom",
+// Section 3.2).  The real product is C' (M' x N') += A' (M' x K') B' (K' x N'):
+//   mdbl: M' = 2m -- C and A complex: Re/Im of A and C become separate rows
+//         (case 2ac; in case 3 together with kdbl this is the 1e/1r pairing
+//         of Eq. 1mc);
+//   ndbl: N' = 2n -- C and B complex, A real: Re/Im of B and C become
+//         separate columns (case 2bc);
+//   kdbl: K' = 2k -- A and B complex: Re/Im of A and B interleave along the
+//         inner dimension (case 2ab, and case 3).
+// Operand parts that cannot reach C (Im(A) in 1a, Im(B) in 1b) are never
+// staged; operand parts that are implicitly zero (Im(B) in 2ac, Im(A) in 2bc)
+// generate no work.
+struct Lowering {
+    bool c_cplx, a_cplx, b_cplx;
+    bool mdbl, ndbl, kdbl;
+    int flop_factor;  // 2, 4 or 8 (x mnk)
+};
+
+inline Lowering lower_case(int cs) {
+    Lowering L{};
+    L.c_cplx = (cs == MD_CASE_1C || cs == MD_CASE_2AC || cs == MD_CASE_2BC || cs == MD_CASE_3);
+    L.a_cplx = (cs == MD_CASE_1A || cs == MD_CASE_2AB || cs == MD_CASE_2AC || cs == MD_CASE_3);
+    L.b_cplx = (cs == MD_CASE_1B || cs == MD_CASE_2AB || cs == MD_CASE_2BC || cs == MD_CASE_3);
+    L.mdbl = (cs == MD_CASE_2AC || cs == MD_CASE_3);
+    L.ndbl = (cs == MD_CASE_2BC);
+    L.kdbl = (cs == MD_CASE_2AB || cs == MD_CASE_3);
+    L.flop_factor = (cs == MD_CASE_3) ? 8 : ((cs == MD_CASE_2AB || cs == MD_CASE_2AC || cs == MD_CASE_2BC) ? 4 : 2);
+    return L;
+}
+
+inline int classify(int dtc, int dta, int dtb) {
+    bool c = dtc >= MD_C, a = dta >= MD_C, b = dtb >= MD_C;
+    if (!c && !a && !b) return MD_CASE_0;
+    if (!c && a && !b) return MD_CASE_1A;
+    if (!c && !a && b) return MD_CASE_1B;
+    if (c && !a && !b) return MD_CASE_1C;
+    if (!c && a && b) return MD_CASE_2AB;
+    if (c && a && !b) return MD_CASE_2AC;
+    if (c && !a && b) return MD_CASE_2BC;
+    return MD_CASE_3;
+}
+
+// Arguments of one product as the kernels see them (all operands already
+// validated; alpha and beta already follow the scalar policies).
+struct GemmArgs {
+    const void *A;
+    const void *B;
+    void *C;
+    int64_t lda, ldb, ldc;  // in elements of each operand's own type
+    int64_t m, n, k;
+    int a_dbl, b_dbl, c_dbl;  // storage precision is double
+    int c_cplx;               // C is complex
+    int ta, tb;               // 0 = 'N', 1 = 'T', 2 = 'C'
+    int a_vec, b_vec;         // 16-byte vector loads are aligned
+    int beta_zero;            // C is not read
+    double alpha_re, alpha_im;
+    double beta_re, beta_im;
+    int tiles_m, tiles_n;     // workgroup tiles of the real product
+};
+
+enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
+
+// Host-side launchers (defined in mdgemm_kernels.hip).
+int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out);
+int launch_scale(const GemmArgs &a, void *stream);
+void tile_shape(int prec, int cs, int *bm, int *bn, int *bk);
+const char *kernel_name(int prec, int cs);
+
+}  // namespace md

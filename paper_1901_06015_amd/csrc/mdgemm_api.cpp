@@ -1,0 +1,186 @@
+// mdgemm_api.cpp -- the C ABI of libmdgemm: argument validation, domain-case
+// classification (Figure "mixeddom"), the computation-precision and scalar
+// policies (Sections 4.1 and 6), quick returns, and dispatch to the kernels.
+#include <stdio.h>
+#include <string.h>
+
+#include "md_internal.h"
+
+using namespace md;
+
+namespace {
+
+int norm_trans(char t) {
+    switch (t) {
+    case 'N': case 'n': return 0;
+    case 'T': case 't': return 1;
+    case 'C': case 'c': return 2;
+    }
+    return -1;
+}
+
+bool dt_ok(int dt) { return dt >= MD_S && dt <= MD_Z; }
+bool dt_cplx(int dt) { return dt == MD_C || dt == MD_Z; }
+bool dt_dbl(int dt) { return dt == MD_D || dt == MD_Z; }
+int dt_bytes(int dt) { return dt == MD_S ? 4 : (dt == MD_Z ? 16 : 8); }
+int64_t max1(int64_t v) { return v > 1 ? v : 1; }
+
+// Everything mdgemm decides before touching the device.
+struct Decision {
+    int status = MD_OK;
+    int cs = MD_CASE_0;
+    int prec = PREC_S;
+    int quick = 0;  // 0 full product, 1 no-op, 2 C := beta*C
+    GemmArgs g{};
+};
+
+Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
+                const void *A, int dta, int64_t lda, const void *B, int dtb, int64_t ldb,
+                md_scalar beta, void *C, int dtc, int64_t ldc, int comp) {
+    Decision d;
+    const int ta = norm_trans(transa), tb = norm_trans(transb);
+    if (ta < 0) { d.status = -1; return d; }
+    if (tb < 0) { d.status = -2; return d; }
+    if (m < 0) { d.status = -3; return d; }
+    if (n < 0) { d.status = -4; return d; }
+    if (k < 0) { d.status = -5; return d; }
+    const bool uses_ab = m > 0 && n > 0 && k > 0 && (alpha.re != 0.0 || alpha.im != 0.0);
+    if (uses_ab && A == nullptr) { d.status = -7; return d; }
+    if (!dt_ok(dta)) { d.status = -8; return d; }
+    if (lda < max1(ta == 0 ? m : k)) { d.status = -9; return d; }
+    if (uses_ab && B == nullptr) { d.status = -10; return d; }
+    if (!dt_ok(dtb)) { d.status = -11; return d; }
+    if (ldb < max1(tb == 0 ? k : n)) { d.status = -12; return d; }
+    if (m > 0 && n > 0 && C == nullptr) { d.status = -14; return d; }
+    if (!dt_ok(dtc)) { d.status = -15; return d; }
+    if (ldc < max1(m)) { d.status = -16; return d; }
+    if (comp != MD_COMP_DEFAULT && comp != MD_COMP_S && comp != MD_COMP_D && comp != MD_COMP_S_BF16X3) {
+        d.status = -17;
+        return d;
+    }
+
+    // Section 4.1.1: the computation precision defaults to C's storage precision.
+    if (comp == MD_COMP_DEFAULT) comp = dt_dbl(dtc) ? MD_COMP_D : MD_COMP_S;
+    d.prec = comp == MD_COMP_D ? PREC_D : (comp == MD_COMP_S ? PREC_S : PREC_BF16X3);
+    d.cs = classify(dtc, dta, dtb);
+
+    // Section 6.2: Im(alpha) is projected away in case 0, used in case 3 and
+    // refused in the six mixed cases.
+    double are = alpha.re, aim = alpha.im;
+    if (d.cs == MD_CASE_0) aim = 0.0;
+    else if (d.cs != MD_CASE_3 && aim != 0.0) { d.status = MD_ERR_ALPHA_IMAG; return d; }
+    // Section 6.2: Im(beta) cannot change a real C.
+    double bre = beta.re, bim = dt_cplx(dtc) ? beta.im : 0.0;
+    // Section 6.1 option (1): beta takes C's storage precision.
+    if (!dt_dbl(dtc)) { bre = (double)(float)bre; bim = (double)(float)bim; }
+
+    GemmArgs &g = d.g;
+    g.A = A; g.B = B; g.C = C;
+    g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.m = m; g.n = n; g.k = k;
+    g.a_dbl = dt_dbl(dta); g.b_dbl = dt_dbl(dtb); g.c_dbl = dt_dbl(dtc);
+    g.c_cplx = dt_cplx(dtc);
+    g.ta = ta; g.tb = tb;
+    // 16-byte loads need an aligned base and column stride, and columns whose
+    // length (in real components) is a multiple of four so that no chunk of
+    // four components straddles the end of a column.
+    const int wa = dt_cplx(dta) ? 2 : 1, wb = dt_cplx(dtb) ? 2 : 1;
+    g.a_vec = ((uintptr_t)A % 16 == 0) && ((lda * dt_bytes(dta)) % 16 == 0) &&
+              (((ta == 0 ? m : k) * wa) % 4 == 0);
+    g.b_vec = ((uintptr_t)B % 16 == 0) && ((ldb * dt_bytes(dtb)) % 16 == 0) &&
+              (((tb == 0 ? k : n) * wb) % 4 == 0);
+    g.alpha_re = are; g.alpha_im = aim;
+    g.beta_re = bre; g.beta_im = bim;
+    g.beta_zero = (bre == 0.0 && bim == 0.0);
+
+    if (m == 0 || n == 0) { d.quick = 1; return d; }
+    if (k == 0 || (are == 0.0 && aim == 0.0)) { d.quick = 2; return d; }
+
+    const Lowering L = lower_case(d.cs);
+    int bm, bn, bk;
+    tile_shape(d.prec, d.cs, &bm, &bn, &bk);
+    const int64_t tmn_a = bm / (L.mdbl ? 2 : 1), tmn_b = bn / (L.ndbl ? 2 : 1);
+    g.tiles_m = (int)((m + tmn_a - 1) / tmn_a);
+    g.tiles_n = (int)((n + tmn_b - 1) / tmn_b);
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
+           const void *A, md_dt dta, int64_t lda, const void *B, md_dt dtb, int64_t ldb,
+           md_scalar beta, void *C, md_dt dtc, int64_t ldc, md_comp comp, void *stream) {
+    Decision d = decide(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C, dtc,
+                        ldc, comp);
+    if (d.status != MD_OK) return d.status;
+    if (d.quick == 1) return MD_OK;
+    if (d.quick == 2) return launch_scale(d.g, stream);
+    if ((int64_t)d.g.tiles_m * d.g.tiles_n > 0x7fffffffLL) return MD_ERR_UNSUPPORTED;
+    return launch_gemm(d.prec, d.cs, d.g, stream, nullptr);
+}
+
+int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
+                const void *A, md_dt dta, int64_t lda, const void *B, md_dt dtb, int64_t ldb,
+                md_scalar beta, void *C, md_dt dtc, int64_t ldc, md_comp comp, md_plan *out) {
+    if (!out) return MD_ERR_STATE;
+    memset(out, 0, sizeof(*out));
+    Decision d = decide(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C, dtc,
+                        ldc, comp);
+    out->status = d.status;
+    if (d.status < 0) return d.status;
+    out->domain_case = d.cs;
+    out->comp = d.prec == PREC_D ? MD_COMP_D : (d.prec == PREC_S ? MD_COMP_S : MD_COMP_S_BF16X3);
+    if (d.status != MD_OK) return d.status;
+    out->quick = d.quick;
+    const Lowering L = lower_case(d.cs);
+    out->a_parts = (L.mdbl || L.kdbl) ? 2 : 1;
+    out->b_parts = (L.ndbl || L.kdbl) ? 2 : 1;
+    out->m_real = m * (L.mdbl ? 2 : 1);
+    out->n_real = n * (L.ndbl ? 2 : 1);
+    out->k_real = k * (L.kdbl ? 2 : 1);
+    if (d.quick == 0) {
+        out->flops = (double)L.flop_factor * (double)m * (double)n * (double)k;
+        int bm, bn, bk;
+        tile_shape(d.prec, d.cs, &bm, &bn, &bk);
+        out->tile_m = bm; out->tile_n = bn; out->tile_k = bk;
+        out->workgroups = (int64_t)d.g.tiles_m * d.g.tiles_n;
+        snprintf(out->kernel, sizeof(out->kernel), "%s", kernel_name(d.prec, d.cs));
+    } else if (d.quick == 2) {
+        snprintf(out->kernel, sizeof(out->kernel), "md_scale_kernel");
+    }
+    return d.status;
+}
+
+const char *mdgemm_strerror(int status) {
+    if (status == MD_OK) return "success";
+    if (status < 0) {
+        static const char *args[] = {"?", "transa", "transb", "m", "n", "k", "alpha", "A", "dta",
+                                     "lda", "B", "dtb", "ldb", "beta", "C", "dtc", "ldc", "comp",
+                                     "stream"};
+        int i = -status;
+        if (i <= 18) return args[i];
+        return "invalid argument in a grouped descriptor";
+    }
+    switch (status) {
+    case MD_ERR_ALPHA_IMAG: return "Im(alpha) != 0 is not supported in cases 1a, 1b, 1c, 2ab, 2ac, 2bc";
+    case MD_ERR_HIP: return "HIP launch or runtime error";
+    case MD_ERR_BUDGET: return "request exceeds the memory budget";
+    case MD_ERR_STATE: return "invalid state";
+    case MD_ERR_UNSUPPORTED: return "not supported by this build";
+    }
+    return "unknown status";
+}
+
+const char *mdgemm_version(void) { return "mdgemm 0.1 gfx950"; }
+
+}  // extern "C"
+
+// Placeholders until the grouped kernel and its tile table land: the
+// symbols exist so that the ABI is complete, and they refuse the call.
+extern "C" int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
+    (void)descs; (void)stream;
+    return count == 0 ? MD_OK : MD_ERR_UNSUPPORTED;
+}
+extern "C" int mdgemm_tune_load(const char *path) { return path ? MD_ERR_UNSUPPORTED : MD_OK; }

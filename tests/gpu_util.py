@@ -1,0 +1,84 @@
+"""Helpers for the GPU parity tests: run one product on the device through the
+C ABI and compare it with the CPU oracle on the same seeded host buffers.
+
+Tolerance (elementwise):
+    |C_gpu - C_ref| <= 4 * k * u_x * (|A||B|)_ij + 4 * u_C * |C_ref_ij|
+with u_x the unit roundoff of the computation precision (2^-24 single,
+2^-53 double), u_C that of C's storage precision, |.| the complex modulus,
+(|A||B|)_ij = sum_p |op(A)_ip| |op(B)_pj| as returned by the oracle, and C_ref
+the oracle's exact-input FP64 result.  `extra` adds documented terms where a
+test leaves the regime the bound is stated for.
+"""
+import numpy as np
+import torch
+
+import oracle
+from paper_1901_06015_amd import _lib, api, inputs
+
+U = {"s": 2.0 ** -24, "d": 2.0 ** -53}
+PREC = {"s": "s", "d": "d", "c": "s", "z": "d"}
+SENTINEL = 777.25
+
+
+def to_device(X):
+    """Copy a Fortran-ordered host buffer into a device tensor with the same
+    column-major strides."""
+    ld, cols = X.shape
+    t = torch.empty((max(cols, 1), ld), dtype=api.torch_dtype(
+        {np.float32: "s", np.float64: "d", np.complex64: "c", np.complex128: "z"}[X.dtype.type]),
+        device="cuda").t()[:, :cols]
+    t.copy_(torch.from_numpy(X))
+    return t
+
+
+def run(tc, ta, tb, m, n, k, comp="d", transa="N", transb="N", alpha=1.5, beta=-0.5,
+        dist="uniform", seed=7, pad_a=0, pad_b=0, pad_c=0, stream=None):
+    """Run one product on the GPU.  Returns (gpu result (m,n) complex128,
+    host C after, host inputs dict)."""
+    ar, ac = (m, k) if transa.upper() == "N" else (k, m)
+    br, bc = (k, n) if transb.upper() == "N" else (n, k)
+    A = inputs.matrix(ar, ac, ta, seed * 3 + 1, ld=max(1, ar) + pad_a, dist=dist, pad=SENTINEL)
+    B = inputs.matrix(br, bc, tb, seed * 3 + 2, ld=max(1, br) + pad_b, dist=dist, pad=SENTINEL)
+    C = inputs.matrix(m, n, tc, seed * 3 + 3, ld=max(1, m) + pad_c, dist=dist, pad=SENTINEL)
+    dA, dB, dC = to_device(A), to_device(B), to_device(C)
+    st = _lib.mdgemm(transa, transb, m, n, k, alpha, dA.data_ptr(), ta, A.shape[0],
+                     dB.data_ptr(), tb, B.shape[0], beta, dC.data_ptr(), tc, C.shape[0],
+                     comp, stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    Cout = dC.cpu().numpy()
+    return st, Cout, dict(A=A, B=B, C=C)
+
+
+def reference(tc, ta, tb, m, n, k, ops, transa="N", transb="N", alpha=1.5, beta=-0.5):
+    A, B, C = ops["A"], ops["B"], ops["C"]
+    st, ref, g = oracle.get().gemm(transa, transb, m, n, k, alpha, A, ta, A.shape[0],
+                                   B, tb, B.shape[0], beta, C, tc, C.shape[0])
+    assert st == 0, st
+    return ref, g
+
+
+def bound(tc, comp, k, ref, g, extra=0.0):
+    ux = U[comp if comp in ("s", "d") else ("s" if comp == "bf16x3" else PREC[tc])]
+    uc = U[PREC[tc]]
+    return 4.0 * k * ux * g + 4.0 * uc * np.abs(ref) + extra
+
+
+def check(tc, comp, k, Cout, m, n, ref, g, extra=0.0, what=""):
+    got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+    err = np.abs(got - ref)
+    b = bound(tc, comp, k, ref, g, extra)
+    bad = ~(err <= b)
+    if bad.any():
+        idx = np.argwhere(bad)[0]
+        i, j = int(idx[0]), int(idx[1])
+        raise AssertionError("%s: %d/%d entries outside the bound; first (%d,%d) got %r ref %r "
+                             "err %.3g bound %.3g" % (what, int(bad.sum()), bad.size, i, j,
+                                                      got[i, j], ref[i, j], err[i, j], b[i, j]))
+    return float(np.max(err / np.maximum(b, 1e-300))) if err.size else 0.0
+
+
+def check_padding(X, rows, what):
+    """Rows beyond `rows` (the ld padding) still hold the sentinel."""
+    if X.shape[0] > rows:
+        pad = X[rows:, :]
+        assert np.all(pad == SENTINEL), "%s: ld padding was written" % what

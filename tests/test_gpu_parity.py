@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every test prints the case it is about to run (flushed) so that a failure on
+the device names its combination, shape and entry point.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gpu_util as gu
+import oracle
+from paper_1901_06015_amd import _lib
+
+pytestmark = pytest.mark.gpu
+TAGS = ("s", "d", "c", "z")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _lib.lib()
+    yield
+
+
+def one(tc, ta, tb, m, n, k, comp, transa="N", transb="N", alpha=1.5, beta=-0.5, **kw):
+    say("mdgemm %s%s%s comp=%s %s%s m=%d n=%d k=%d %r" % (tc, ta, tb, comp, transa, transb, m, n, k, kw))
+    st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, transa=transa, transb=transb,
+                           alpha=alpha, beta=beta, **kw)
+    assert st == 0, (st, _lib.strerror(st))
+    ref, g = gu.reference(tc, ta, tb, m, n, k, ops, transa, transb, alpha, beta)
+    r = gu.check(tc, comp, k, Cout, m, n, ref, g, what="%s%s%s/%s" % (tc, ta, tb, comp))
+    gu.check_padding(Cout, m, "C")
+    return r, Cout, ref, ops
+
+
+@pytest.mark.parametrize("comp", ["s", "d"])
+@pytest.mark.parametrize("tc", TAGS)
+def test_all_storage_combinations(tc, comp):
+    """All 16 (A, B) storage pairs for this C and computation precision, at a
+    size that spans several workgroup tiles and k tiles with ragged edges."""
+    for ta, tb in itertools.product(TAGS, TAGS):
+        one(tc, ta, tb, 150, 140, 70, comp)
+
+
+@pytest.mark.parametrize("transa,transb", list(itertools.product("NTC", "NTC")))
+def test_transpose_variants(transa, transb):
+    """The nine op(A), op(B) combinations of Section 1, on a combination of
+    every domain case."""
+    combos = ["ddd", "sdc", "dzs", "scz", "csd", "zdz", "czs", "zcz"]
+    for i, cab in enumerate(combos):
+        comp = "sd"[i % 2]
+        one(cab[0], cab[1], cab[2], 77, 93, 41, comp, transa, transb)
+
+
+@pytest.mark.parametrize("comp", ["s", "d"])
+def test_exact_inputs_bitwise(comp):
+    """Integer entries in [-4, 4], alpha = 1.5, beta = -0.5: every rounding in
+    either precision is exact, so the GPU must equal the oracle bit for bit,
+    whatever its summation order."""
+    for tc, ta, tb in itertools.product(TAGS, TAGS, TAGS):
+        say("exact %s%s%s comp=%s" % (tc, ta, tb, comp))
+        m, n, k = 70, 66, 45
+        st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, dist="int", seed=11)
+        assert st == 0
+        ref, _ = gu.reference(tc, ta, tb, m, n, k, ops)
+        got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+        assert np.array_equal(got, ref), "exact %s%s%s/%s: %d mismatches" % (
+            tc, ta, tb, comp, int((got != ref).sum()))
+
+
+@pytest.mark.parametrize("cab", ["zcd", "ccs", "zzz", "sdd", "dcz", "csz", "zss", "szc"])
+def test_edge_sizes(cab):
+    """Tile edges and degenerate sizes (0 and 1 included), both precisions."""
+    sizes = (0, 1, 2, 3, 5, 17, 33, 65, 129)
+    rng = np.random.Generator(np.random.PCG64(5))
+    for comp in ("s", "d"):
+        for _ in range(10):
+            m, n, k = (int(x) for x in rng.choice(sizes, 3))
+            one(cab[0], cab[1], cab[2], m, n, k, comp)
+
+
+def test_unaligned_leading_dimensions():
+    """Odd leading dimensions defeat 16-byte loads: the component-wise load
+    path must give the same result; the padding rows are never written."""
+    for cab, comp in (("zcd", "d"), ("sds", "s"), ("czz", "s"), ("dzc", "d")):
+        one(cab[0], cab[1], cab[2], 131, 67, 53, comp, pad_a=1, pad_b=3, pad_c=5)
+        one(cab[0], cab[1], cab[2], 131, 67, 53, comp, "T", "C", pad_a=2, pad_b=1, pad_c=2)
+
+
+def test_complex_scalars_case3():
+    """Case 3 uses a complex alpha and a complex beta (Section 6.2)."""
+    for cab in ("zzz", "ccc", "zcz", "czc"):
+        assert oracle.get().case(cab[0], cab[1], cab[2]) == "3"
+        for comp in ("s", "d"):
+            one(cab[0], cab[1], cab[2], 90, 70, 50, comp, alpha=0.75 - 0.5j, beta=0.5 + 0.25j)
+
+
+def test_complex_beta_mixed_cases():
+    """Complex beta is honoured whenever C is complex (cases 1c, 2ac, 2bc);
+    a complex beta on a real C acts through Re(beta) only."""
+    for cab in ("zdd", "czs", "zsz", "dcz", "sdc"):
+        for comp in ("s", "d"):
+            one(cab[0], cab[1], cab[2], 70, 50, 30, comp, alpha=1.25, beta=0.5 - 0.75j)
+
+
+def test_case_1c_imaginary_part():
+    """Case 1c: AB reaches only Re(C); Im(C) is beta*Im(C) exactly (beta real)."""
+    for tc in ("c", "z"):
+        for beta in (1.0, -0.5):
+            _, Cout, ref, ops = one(tc, "d", "s", 100, 60, 40, "s", beta=beta)
+            C0 = ops["C"][:100, :60]
+            assert np.array_equal(Cout[:100, :60].imag, (beta * C0.imag).astype(C0.imag.dtype))
+
+
+def test_beta_zero_does_not_read_c_and_alpha_zero_does_not_read_ab():
+    import torch as T
+    m, n, k = 40, 30, 20
+    for cab in ("zcd", "sss", "dzz"):
+        tc, ta, tb = cab
+        A = gu.to_device(gu.inputs.matrix(m, k, ta, 1))
+        B = gu.to_device(gu.inputs.matrix(k, n, tb, 2))
+        C = gu.to_device(gu.inputs.matrix(m, n, tc, 3))
+        C.fill_(float("nan"))
+        say("beta=0 NaN C", cab)
+        st = _lib.mdgemm("N", "N", m, n, k, 1.0, A.data_ptr(), ta, m, B.data_ptr(), tb, k, 0.0,
+                         C.data_ptr(), tc, m, None, T.cuda.current_stream().cuda_stream)
+        T.cuda.synchronize()
+        assert st == 0 and bool(T.isfinite(C).all())
+        A.fill_(float("nan"))
+        C2h = gu.inputs.matrix(m, n, tc, 4)
+        C2 = gu.to_device(C2h)
+        say("alpha=0 NaN A", cab)
+        st = _lib.mdgemm("N", "N", m, n, k, 0.0, A.data_ptr(), ta, m, B.data_ptr(), tb, k, -0.5,
+                         C2.data_ptr(), tc, m, None, T.cuda.current_stream().cuda_stream)
+        T.cuda.synchronize()
+        assert st == 0
+        assert np.array_equal(C2.cpu().numpy(), (-0.5 * C2h).astype(C2h.dtype))
+
+
+def test_error_leaves_c_untouched():
+    m, n, k = 16, 16, 16
+    A = gu.to_device(gu.inputs.matrix(m, k, "c", 1))
+    B = gu.to_device(gu.inputs.matrix(k, n, "s", 2))
+    Ch = gu.inputs.matrix(m, n, "s", 3)
+    C = gu.to_device(Ch)
+    st = _lib.mdgemm("N", "N", m, n, k, 1.0 + 1.0j, A.data_ptr(), "c", m, B.data_ptr(), "s", k,
+                     1.0, C.data_ptr(), "s", m, None, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert st == _lib.MD_ERR_ALPHA_IMAG
+    assert np.array_equal(C.cpu().numpy(), Ch)
+
+
+def test_paper_config_zcdd_256():
+    """Single mixed GEMM: m=n=k=256, A single complex, B double real, C double
+    complex, double computation, alpha = beta = 1, full oracle comparison."""
+    one("z", "c", "d", 256, 256, 256, "d", alpha=1.0, beta=1.0, seed=2019)
+
+
+def test_stream_argument():
+    """Work is enqueued on the caller's stream."""
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        st, Cout, ops = gu.run("z", "z", "d", 64, 64, 64, comp="d", stream=s.cuda_stream)
+    assert st == 0
+    ref, g = gu.reference("z", "z", "d", 64, 64, 64, ops)
+    gu.check("z", "d", 64, Cout, 64, 64, ref, g)
