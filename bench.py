@@ -1,0 +1,297 @@
+"""Benchmark: mixed-datatype GEMM on one MI355X.
+
+Workload (one "step"): the full sweep of the plain method -- all 64 storage
+combinations of (C, A, B) in {s, d, c, z}^3 times computation precision
+{single, double} = 128 products, each m = n = k = 4096, column-major, entries
+U[-1, 1] per real/imaginary part (seeded), alpha = 1.5, beta = -0.5, no
+transpose.  Inputs are resident in HBM before timing starts.
+
+Reported (one JSON line):
+  value        aggregate GFLOP/s of the sweep: sum of the paper's minimum flop
+               counts (2/4/8 mnk per case) / time of the step
+  per_combo    per combination: p50 GFLOP/s, p50/p99 latency, and the ratio to
+               the same-GPU native kernel the paper uses as its reference
+               (sgemm/dgemm for cases 0-2, cgemm/zgemm for case 3, at the
+               computation precision; torch.matmul -> hipBLASLt/rocBLAS)
+  roofline     dominant kernel's achieved TFLOP/s (algorithmic flops / its
+               measured duration, HIP events on its stream) vs the MFMA peak
+  cpu_baseline the FP64 oracle timed on this host on a bounded sample
+
+    python bench.py [--steps K] [--warmup W] [--size N] [--combos zcd,sss] [--no-cpu]
+"""
+import argparse
+import hashlib
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+TAGS = ("s", "d", "c", "z")
+CASE_FACTOR = {"0": 2, "1a": 2, "1b": 2, "1c": 2, "2ab": 4, "2ac": 4, "2bc": 4, "3": 8}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--size", type=int, default=4096)
+    p.add_argument("--combos", type=str, default="", help="comma list like zcdd,ssss (cabx)")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-native", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def combos(filter_str):
+    out = []
+    for tc, ta, tb in itertools.product(TAGS, TAGS, TAGS):
+        for x in ("s", "d"):
+            out.append(tc + ta + tb + x)
+    if filter_str:
+        keep = set(filter_str.split(","))
+        out = [c for c in out if c in keep]
+    return out
+
+
+def make_operands(n, seed=1901):
+    """One A, B and C per storage type, resident on the device."""
+    import torch
+    from paper_1901_06015_amd import inputs
+    ops = {}
+    for role, off in (("A", 0), ("B", 100), ("C", 200)):
+        for dt in TAGS:
+            h = inputs.matrix(n, n, dt, seed + off + TAGS.index(dt))
+            t = torch.from_numpy(h).cuda()
+            assert t.stride(0) == 1
+            ops[role + dt] = t
+            del h
+    return ops
+
+
+def native_times(n, reps=10):
+    """p50 seconds of torch.matmul per dtype (the native same-type GEMM)."""
+    import torch
+    res = {}
+    for name, dt, fl in (("sgemm", torch.float32, 2), ("dgemm", torch.float64, 2),
+                         ("cgemm", torch.complex64, 8), ("zgemm", torch.complex128, 8)):
+        g = torch.Generator(device="cuda").manual_seed(5)
+        if dt.is_complex:
+            rdt = torch.float32 if dt == torch.complex64 else torch.float64
+            a = torch.complex(torch.rand(n, n, device="cuda", dtype=rdt, generator=g) * 2 - 1,
+                              torch.rand(n, n, device="cuda", dtype=rdt, generator=g) * 2 - 1)
+            b = torch.complex(torch.rand(n, n, device="cuda", dtype=rdt, generator=g) * 2 - 1,
+                              torch.rand(n, n, device="cuda", dtype=rdt, generator=g) * 2 - 1)
+        else:
+            a = torch.rand(n, n, device="cuda", dtype=dt, generator=g) * 2 - 1
+            b = torch.rand(n, n, device="cuda", dtype=dt, generator=g) * 2 - 1
+        c = torch.empty(n, n, device="cuda", dtype=dt)
+        for _ in range(3):
+            torch.matmul(a, b, out=c)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch.matmul(a, b, out=c)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        res[name] = {"p50_s": float(np.median(ts)), "gflops": fl * n ** 3 / float(np.median(ts)) / 1e9}
+        del a, b, c
+        torch.cuda.empty_cache()
+    return res
+
+
+def native_for(case, x):
+    if case == "3":
+        return "cgemm" if x == "s" else "zgemm"
+    return "sgemm" if x == "s" else "dgemm"
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    src = os.path.join(ROOT, "paper_1901_06015_amd", "csrc", "mdgemm_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    ent = rec.get(kernel)
+    if not ent or ent.get("kernel_src_sha256") != sha:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(budget_s):
+    """The oracle, as it is, timed single-threaded on this host: full columns
+    of C for dddd, zcdd and zzzd at 4096 (the sample), GFLOP/s counted with
+    the same algorithmic flops as the GPU."""
+    import oracle
+    from paper_1901_06015_amd import inputs
+    o = oracle.get()
+    n = 4096
+    total_fl, total_t, cols_done = 0.0, 0.0, {}
+    per = budget_s / 3.0
+    for cab in ("ddd", "zcd", "zzz"):
+        tc, ta, tb = cab
+        A = inputs.matrix(n, n, ta, 11)
+        B = inputs.matrix(n, n, tb, 12)
+        C = inputs.matrix(n, n, tc, 13)
+        fac = CASE_FACTOR[o.case(tc, ta, tb)]
+        t0 = time.perf_counter()
+        j = 0
+        while time.perf_counter() - t0 < per:
+            rows = np.arange(n, dtype=np.int64)
+            cols = np.full(n, j, dtype=np.int64)
+            st, _, _ = o.gemm_at("N", "N", n, n, n, 1.5, A, ta, n, B, tb, n, -0.5, C, tc, n, rows, cols)
+            assert st == 0
+            j += 1
+        dt = time.perf_counter() - t0
+        total_fl += fac * n * n * j
+        total_t += dt
+        cols_done[cab + "d"] = j
+    return {"value": total_fl / total_t / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "full columns of C at m=n=k=4096 for %s (single thread, FP64 triple loop, %.1f s)"
+                      % (", ".join("%s:%d cols" % kv for kv in cols_done.items()), total_t)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1901_06015_amd import _lib, api
+    _lib.lib()
+    n = args.size
+    todo = combos(args.combos)
+    print("# bench: %d combinations at %d^3" % (len(todo), n), file=sys.stderr, flush=True)
+    ops = make_operands(n)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    plans = {}
+    for cabx in todo:
+        tc, ta, tb, x = cabx
+        st, p = _lib.mdgemm_plan("N", "N", n, n, n, 1.5, ops["A" + ta].data_ptr(), ta, n,
+                                 ops["B" + tb].data_ptr(), tb, n, -0.5, ops["C" + tc].data_ptr(), tc, n, x)
+        assert st == 0, (cabx, st)
+        plans[cabx] = p
+
+    def launch(cabx):
+        tc, ta, tb, x = cabx
+        st = _lib.mdgemm("N", "N", n, n, n, 1.5, ops["A" + ta].data_ptr(), ta, n,
+                         ops["B" + tb].data_ptr(), tb, n, -0.5, ops["C" + tc].data_ptr(), tc, n, x, sp)
+        if st != 0:
+            raise RuntimeError("mdgemm %s failed: %d" % (cabx, st))
+
+    for w in range(args.warmup):
+        for cabx in todo:
+            launch(cabx)
+        torch.cuda.synchronize()
+        print("# warmup %d done" % w, file=sys.stderr, flush=True)
+
+    times = {c: [] for c in todo}
+    step_ms = []
+    for s in range(args.steps):
+        evs = []
+        torch.cuda.synchronize()
+        e_start = torch.cuda.Event(enable_timing=True)
+        e_start.record(stream)
+        prev = e_start
+        for cabx in todo:
+            launch(cabx)
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            evs.append((cabx, prev, e))
+            prev = e
+        torch.cuda.synchronize()
+        for cabx, a, b in evs:
+            times[cabx].append(a.elapsed_time(b) / 1e3)
+        step_ms.append(e_start.elapsed_time(prev))
+        print("# step %d: %.1f ms" % (s, step_ms[-1]), file=sys.stderr, flush=True)
+
+    flops = {c: plans[c]["flops"] for c in todo}
+    step_flops = sum(flops.values())
+    ms = float(np.median(step_ms))
+    value = step_flops / (ms / 1e3) / 1e9
+
+    native = native_times(n) if not args.no_native else {}
+    per = {}
+    by_kernel = {}
+    for c in todo:
+        ts = np.array(times[c])
+        p50 = float(np.median(ts))
+        gf = flops[c] / p50 / 1e9
+        nat = native.get(native_for(plans[c]["case"], c[3]))
+        per[c] = {"case": plans[c]["case"], "gflops": round(gf, 1),
+                  "vs_native": round(gf / nat["gflops"], 3) if nat else None,
+                  "p50_ms": round(p50 * 1e3, 4), "p99_ms": round(float(np.percentile(ts, 99)) * 1e3, 4)}
+        k = plans[c]["kernel"]
+        bk = by_kernel.setdefault(k, {"flops": 0.0, "time": 0.0, "launches": 0})
+        bk["flops"] += flops[c] * len(ts)
+        bk["time"] += float(ts.sum())
+        bk["launches"] += len(ts)
+    dom = max(by_kernel, key=lambda k: by_kernel[k]["time"])
+    dk = by_kernel[dom]
+    prec = "f64" if "_f64_" in dom else "f32"
+    achieved = dk["flops"] / dk["time"] / 1e12
+    ratios = [v["vs_native"] for v in per.values() if v["vs_native"] is not None]
+    out = {
+        "metric": "GFLOP/s per type combo at m=n=k=4096 vs native same-type; p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "plain method full sweep: %d of the 128 storage x computation-precision "
+                               "combinations, m=n=k=%d column-major, U[-1,1], alpha=1.5, beta=-0.5, "
+                               "no transpose" % (len(todo), n),
+                   "m": n, "n": n, "k": n, "combos": len(todo)},
+        "latency_ms": {"p50_of_p50": round(float(np.median([v["p50_ms"] for v in per.values()])), 4),
+                       "max_p99": round(max(v["p99_ms"] for v in per.values()), 4)},
+        "vs_native": {"min": min(ratios) if ratios else None,
+                      "median": float(np.median(ratios)) if ratios else None,
+                      "combos_at_or_above_0.9": sum(1 for r in ratios if r >= 0.9)},
+        "native_gflops": {k: round(v["gflops"], 1) for k, v in native.items()},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+                     "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS[prec], 4),
+                     "traffic": traffic_record(dom),
+                     "launches": dk["launches"],
+                     "avg_launch_ms": round(dk["time"] / dk["launches"] * 1e3, 4)},
+        "per_kernel": {k: {"tflops": round(v["flops"] / v["time"] / 1e12, 2),
+                           "avg_ms": round(v["time"] / v["launches"] * 1e3, 4),
+                           "launches": v["launches"]} for k, v in sorted(by_kernel.items())},
+        "per_combo": per,
+    }
+    if not args.no_cpu:
+        print("# cpu baseline (%.0f s)" % args.cpu_seconds, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -25,21 +25,24 @@ HIP_FLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
              "-I" + os.path.join(ROOT, "include")]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
 
-SOURCES = [
-    "mdgemm_kernels.hip",
-    "mdgemm_grouped.hip",
-    "mdgemm_api.cpp",
-    "md_server.cpp",
+# (source, extra defines, object name)
+SOURCES = [("mdgemm_kernels.hip", ["-DMD_KT=%d" % t, "-DMD_KCASE=%d" % c], "k_%d_%d.o" % (t, c))
+           for t in (1, 0) for c in (7, 4, 5, 6, 0, 1, 2, 3)] + [
+    ("mdgemm_launch.hip", [], "launch.o"),
+    ("mdgemm_grouped.hip", [], "grouped.o"),
+    ("mdgemm_api.cpp", [], "api.o"),
+    ("md_server.cpp", [], "server.o"),
 ]
 
 
-def _compile(src):
+def _compile(entry):
+    src, defs, objname = entry
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
+    obj = os.path.join(BUILD, objname)
     if src.endswith(".hip"):
-        cmd = [HIPCC] + HIP_FLAGS + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + HIP_FLAGS + defs + ["-c", path, "-o", obj]
     else:
-        cmd = [HIPCC] + CXX_FLAGS + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + CXX_FLAGS + defs + ["-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), res.stderr))
@@ -48,8 +51,8 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    srcs = [e for e in SOURCES if os.path.exists(os.path.join(CSRC, e[0]))]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(int(os.environ.get('MAX_JOBS', '8')), len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]

@@ -73,6 +73,6 @@ enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
 int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out);
 int launch_scale(const GemmArgs &a, void *stream);
 void tile_shape(int prec, int cs, int *bm, int *bn, int *bk);
-const char *kernel_name(int prec, int cs);
+void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len);
 
 }  // namespace md

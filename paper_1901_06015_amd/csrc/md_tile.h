@@ -1,0 +1,518 @@
+// md_tile.h -- device side of libmdgemm for gfx950 (CDNA4): the product kernel
+// template, instantiated by mdgemm_kernels.hip.
+//
+// One templated kernel per (computation precision, domain case).  Each
+// workgroup owns a tile of the real product C' += A' B' that its case lowers
+// to (md_internal.h, Figure "mixeddom"):
+//
+//   1. cast-on-pack: A and B tiles are read from HBM in their storage type
+//      with 16-byte vector loads, converted to the computation type in
+//      registers (float -> double exact, double -> float round-to-nearest-even,
+//      the typecasting pack of Section 4) and written to LDS already in the
+//      layout of the real product: complex elements are split into their
+//      parts, the parts that cannot reach C are dropped, conjugation flips a
+//      sign, and case 3 writes A in the 1e arrangement of Eq. 1mc (each complex
+//      element becomes the real 2x2 block [re -im; im re]) while B keeps the
+//      1r arrangement (re, im interleaved along k);
+//   2. a double-buffered k loop of real MFMA (v_mfma_f64_16x16x4f64 or
+//      v_mfma_f32_16x16x4f32) over the LDS tiles: the global loads of tile t+1
+//      are in flight while tile t is multiplied;
+//   3. an epilogue that applies alpha (cast to the computation precision) and
+//      beta (cast to C's storage precision), forms beta*C + alpha*AB in the
+//      wider of the computation and C precisions, and rounds once to C's
+//      storage type (Sections 4.1.3 and 6.1).
+//
+// The MFMA is issued with B' as its first operand so that the accumulator
+// lanes run along m: stores to column-major C are then contiguous.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#pragma once
+#include "md_internal.h"
+
+namespace md {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;  // threads per workgroup: 4 waves of 64
+constexpr int G = 16;    // MFMA block edge (16x16 output blocks)
+
+template <class T> struct TileCfg;
+template <> struct TileCfg<double> {
+    static constexpr int BM = 128, BN = 128, BK = 16, PAD = 16;
+};
+template <> struct TileCfg<float> {
+    static constexpr int BM = 128, BN = 128, BK = 32, PAD = 16;
+};
+
+template <class T> struct AccT;
+template <> struct AccT<double> { typedef v4d type; };
+template <> struct AccT<float> { typedef v4f type; };
+
+__device__ __forceinline__ v4d mfma16(double x, double y, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(float x, float y, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+}
+
+// Row (inside a 16x16 block) of accumulator item v held by `lane`; the column
+// is lane & 15.  The two 16x16x4 instructions lay their results out
+// differently (measured on gfx950).
+template <class T> __device__ __forceinline__ int acc_row(int lane, int v);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int v) { return 4 * v + (lane >> 4); }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+
+// ---------------------------------------------------------------------------
+// Operand staging (cast-on-pack)
+// ---------------------------------------------------------------------------
+enum Mode {
+    M_PLAIN = 0,   // real operand
+    M_REONLY = 1,  // complex operand of which only Re reaches C (1a: A, 1b: B)
+    M_KINT = 2,    // complex; Re/Im interleaved along k (2ab: A and B; 3: B = 1r)
+    M_MNINT = 3,   // complex; Re/Im as separate rows/columns (2ac: A; 2bc: B)
+    M_ONEE = 4     // complex A of case 3 in the 1e arrangement
+};
+
+template <int CS, bool IS_A> __host__ __device__ constexpr int mode_of() {
+    if (IS_A) {
+        return CS == MD_CASE_1A ? M_REONLY
+             : CS == MD_CASE_2AB ? M_KINT
+             : CS == MD_CASE_2AC ? M_MNINT
+             : CS == MD_CASE_3 ? M_ONEE : M_PLAIN;
+    }
+    return CS == MD_CASE_1B ? M_REONLY
+         : (CS == MD_CASE_2AB || CS == MD_CASE_3) ? M_KINT
+         : CS == MD_CASE_2BC ? M_MNINT : M_PLAIN;
+}
+
+// Real row (or column) of the tile that holds part q of complex index mm when
+// Re/Im are split: blocks of G alternate Re, Im so that both parts of one
+// complex element land in the same lane of the same MFMA block pair.
+__device__ __forceinline__ int split_pos(int mm, int q) { return (((mm >> 4) << 1) + q) * G + (mm & 15); }
+
+template <class T, int CS, bool IS_A, bool FAST, bool SDBL>
+struct Stage {
+    typedef TileCfg<T> C;
+    static constexpr int MODE = mode_of<CS, IS_A>();
+    static constexpr int W = (MODE == M_PLAIN) ? 1 : 2;  // stored components per element
+    static constexpr bool MN2 = (MODE == M_MNINT || MODE == M_ONEE);
+    static constexpr bool K2 = (MODE == M_KINT || MODE == M_ONEE);
+    static constexpr int BMN = IS_A ? C::BM : C::BN;
+    static constexpr int TMN = BMN / (MN2 ? 2 : 1);  // stored m (or n) extent of a tile
+    static constexpr int TK = C::BK / (K2 ? 2 : 1);   // stored k extent of a tile
+    static constexpr int CHUNKS = TMN * TK * W / 4;   // 4 components per chunk
+    static constexpr int PER = CHUNKS / NT;
+    static constexpr int LDW = BMN + C::PAD;          // LDS row stride (elements)
+    static constexpr int ESZ = SDBL ? 8 : 4;          // bytes per stored component
+    static constexpr int NV = SDBL ? 2 : 1;           // 16-byte vectors per chunk
+    // chunks per stored column of a tile, for either layout (powers of two)
+    static constexpr int CPC_MN = TMN * W / 4, CPC_K = TK * W / 4;
+    // Sign applied to Im when it is placed at an odd k' row: -Im(A) in case 2ab
+    // realises Re(AB) = ArBr - AiBi; B's Im enters positively.
+    static constexpr bool KNEG = IS_A;
+    static_assert(CHUNKS % NT == 0, "tile does not split evenly over the workgroup");
+    static_assert((TMN * W) % 4 == 0 && (TK * W) % 4 == 0, "chunks straddle columns");
+    static_assert((CPC_MN & (CPC_MN - 1)) == 0 && (CPC_K & (CPC_K - 1)) == 0 && CPC_MN <= NT && CPC_K <= NT,
+                  "chunk grid must be a power of two no wider than the workgroup");
+
+    // Registers holding one tile's loads until they are converted.
+    struct Chunk { uint4 v[NV]; };
+    Chunk raw[PER];
+
+    const char *base;
+    int64_t ld, MN, K, mn0;
+    int64_t total_bytes;  // extent of the stored matrix
+    bool mn_contig, conj;
+    int cpc_log;          // log2 of chunks per stored column inside a tile
+    int pos, col0;        // this thread's chunk 0: position in its column, column in the tile
+    int col_step;         // columns between a thread's consecutive chunks
+
+    __device__ __forceinline__ Stage(const GemmArgs &g, int tid, int64_t mn0_) {
+        const int tr = IS_A ? g.ta : g.tb;
+        mn_contig = IS_A ? (tr == 0) : (tr != 0);
+        conj = (tr == 2);
+        ld = IS_A ? g.lda : g.ldb;
+        MN = IS_A ? g.m : g.n;
+        K = g.k;
+        mn0 = mn0_;
+        base = (const char *)(IS_A ? g.A : g.B);
+        const int cpc = mn_contig ? CPC_MN : CPC_K;
+        cpc_log = __builtin_ctz(cpc);
+        pos = tid & (cpc - 1);
+        col0 = tid >> cpc_log;
+        col_step = NT >> cpc_log;
+        const int64_t rows_st = mn_contig ? MN : K, cols_st = mn_contig ? K : MN;
+        total_bytes = ((cols_st - 1) * ld + rows_st) * W * ESZ;
+    }
+
+    // FAST path: buffer loads.  A chunk outside the matrix gets an offset
+    // beyond the resource's range and reads as zero, with no branch.
+    __device__ __forceinline__ void load_fast(int t) {
+        const int64_t k0 = (int64_t)t * TK;
+        const int64_t base_off = (mn_contig ? (k0 * ld + mn0) : (mn0 * ld + k0)) * W * ESZ;
+        const int64_t rem = total_bytes - base_off;
+        const int nrec = rem > 0x7fffffffLL ? 0x7fffffff : (rem < 0 ? 0 : (int)rem);
+        __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(base + base_off), (short)0, nrec, 0x00020000);
+        const int64_t lim64 = K - k0;
+        const int klim = lim64 > (1 << 30) ? (1 << 30) : (int)lim64;
+        const int64_t mlim64 = MN - mn0;
+        const int mlim = mlim64 > (1 << 30) ? (1 << 30) : (int)mlim64;
+        const uint32_t col_bytes = (uint32_t)(ld * W * ESZ);
+        const int epos = (pos * 4) / W;  // first element of the chunk along the contiguous dim
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            const int col = col0 + c * col_step;
+            // element index along m/n and along k of this chunk's first element
+            const int e_mn = mn_contig ? epos : col;
+            const int e_k = mn_contig ? col : epos;
+            const bool ok = (e_mn < mlim) && (e_k < klim);
+            const uint32_t off = ok ? (uint32_t)col * col_bytes + (uint32_t)(pos * 4 * ESZ) : 0x80000000u;
+#pragma unroll
+            for (int h = 0; h < NV; ++h) {
+                const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u * h), 0, 0);
+                raw[c].v[h] = make_uint4(x[0], x[1], x[2], x[3]);
+            }
+        }
+    }
+
+    // Generic path: any alignment and leading dimension; components are
+    // loaded one by one and anything outside the matrix reads as zero.
+    __device__ __forceinline__ void load_generic(int t) {
+        const int64_t k0 = (int64_t)t * TK;
+        const int64_t rows_st = mn_contig ? MN : K, cols_st = mn_contig ? K : MN;
+        const int64_t r0 = mn_contig ? mn0 : k0, c0 = mn_contig ? k0 : mn0;
+        const int64_t contig_len = rows_st * W, col_stride = ld * W;
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            const int64_t col = c0 + col0 + c * col_step, comp0 = r0 * W + pos * 4;
+            const bool colok = col < cols_st;
+            const int64_t idx = col * col_stride + comp0;
+            if constexpr (SDBL) {
+                const uint2 *p = (const uint2 *)base + idx;
+                uint2 e0 = make_uint2(0u, 0u), e1 = e0, e2 = e0, e3 = e0;
+                if (colok && comp0 + 0 < contig_len) e0 = p[0];
+                if (colok && comp0 + 1 < contig_len) e1 = p[1];
+                if (colok && comp0 + 2 < contig_len) e2 = p[2];
+                if (colok && comp0 + 3 < contig_len) e3 = p[3];
+                raw[c].v[0] = make_uint4(e0.x, e0.y, e1.x, e1.y);
+                raw[c].v[NV - 1] = make_uint4(e2.x, e2.y, e3.x, e3.y);
+            } else {
+                const uint32_t *p = (const uint32_t *)base + idx;
+                uint32_t e0 = 0u, e1 = 0u, e2 = 0u, e3 = 0u;
+                if (colok && comp0 + 0 < contig_len) e0 = p[0];
+                if (colok && comp0 + 1 < contig_len) e1 = p[1];
+                if (colok && comp0 + 2 < contig_len) e2 = p[2];
+                if (colok && comp0 + 3 < contig_len) e3 = p[3];
+                raw[c].v[0] = make_uint4(e0, e1, e2, e3);
+            }
+        }
+    }
+
+    // Issue the global loads of k-tile t.
+    __device__ __forceinline__ void load(int t) {
+        if constexpr (FAST) load_fast(t);
+        else load_generic(t);
+    }
+
+    // Component q of a chunk converted to the computation type (the
+    // typecasting pack: float -> double exact, double -> float nearest-even).
+    __device__ __forceinline__ static T component(const Chunk &x, int q) {
+        if constexpr (SDBL) {
+            const uint4 h = x.v[q >> 1];
+            const uint32_t w0 = (q & 1) ? h.z : h.x;
+            const uint32_t w1 = (q & 1) ? h.w : h.y;
+            return (T)__builtin_bit_cast(double, ((uint64_t)w1 << 32) | w0);
+        } else {
+            const uint4 h = x.v[0];
+            const uint32_t w = q == 0 ? h.x : (q == 1 ? h.y : (q == 2 ? h.z : h.w));
+            return (T)__builtin_bit_cast(float, w);
+        }
+    }
+
+    __device__ __forceinline__ static void emit(T *lds, int mm, int kk, int part, T v, bool conj) {
+        if constexpr (MODE == M_PLAIN) {
+            lds[kk * LDW + mm] = v;
+        } else if constexpr (MODE == M_REONLY) {
+            if (part == 0) lds[kk * LDW + mm] = v;
+        } else {
+            const T vi = conj ? -v : v;
+            if constexpr (MODE == M_KINT) {
+                if (part == 0) lds[(2 * kk) * LDW + mm] = v;
+                else lds[(2 * kk + 1) * LDW + mm] = KNEG ? -vi : vi;
+            } else if constexpr (MODE == M_MNINT) {
+                if (part == 0) lds[kk * LDW + split_pos(mm, 0)] = v;
+                else lds[kk * LDW + split_pos(mm, 1)] = vi;
+            } else {  // M_ONEE: [re -im; im re] per complex element (Eq. 1mc)
+                if (part == 0) {
+                    lds[(2 * kk) * LDW + split_pos(mm, 0)] = v;
+                    lds[(2 * kk + 1) * LDW + split_pos(mm, 1)] = v;
+                } else {
+                    lds[(2 * kk) * LDW + split_pos(mm, 1)] = vi;
+                    lds[(2 * kk + 1) * LDW + split_pos(mm, 0)] = -vi;
+                }
+            }
+        }
+    }
+
+    // Convert the staged registers and write them to one LDS buffer.  `part`
+    // (Re/Im) is known at compile time; the layout choice is a select.
+    __device__ __forceinline__ void store(T *lds) const {
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            const int col = col0 + c * col_step;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const T v = component(raw[c], q);
+                const int e = pos * (4 / W) + q / W;
+                const int part = q % W;
+                const int mm = mn_contig ? e : col;
+                const int kk = mn_contig ? col : e;
+                emit(lds, mm, kk, part, v, conj);
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Workgroup -> tile mapping.  Workgroups are dealt round-robin to the 8 XCDs
+// (each with its own L2); renumber so that each XCD gets a contiguous range of
+// tiles, then walk that range in column groups of GROUP_M row-tiles so
+// neighbouring workgroups share A row-panels and B column-panels in L2.
+// ---------------------------------------------------------------------------
+constexpr int NXCD = 8;
+constexpr int GROUP_M = 8;
+
+__device__ __forceinline__ void map_tile(int wg, int nwg, int tiles_m, int tiles_n, int *tm, int *tn) {
+    const int q = nwg / NXCD, r = nwg % NXCD;
+    const int xcd = wg % NXCD, local = wg / NXCD;
+    const int lin = (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    const int group = GROUP_M * tiles_n;
+    const int gid = lin / group;
+    const int first_m = gid * GROUP_M;
+    const int gm = min(tiles_m - first_m, GROUP_M);
+    const int in = lin - gid * group;
+    *tm = first_m + in % gm;
+    *tn = in / gm;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue: C := beta*C + alpha*AB, rounded once to C's storage type
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void update_real(const GemmArgs &g, int64_t i, int64_t j, T acc) {
+    if (i >= g.m || j >= g.n) return;
+    const int64_t off = i + j * g.ldc;
+    const T ax = (T)g.alpha_re;
+    if (g.c_dbl) {
+        double *c = (double *)g.C;
+        const double t = (double)ax * (double)acc;
+        c[off] = g.beta_zero ? t : fma(g.beta_re, c[off], t);
+    } else {
+        float *c = (float *)g.C;
+        const float bc = (float)g.beta_re;
+        if constexpr (sizeof(T) == 8) {
+            const double t = ax * acc;
+            c[off] = (float)(g.beta_zero ? t : fma((double)bc, (double)c[off], t));
+        } else {
+            const float t = ax * acc;
+            c[off] = g.beta_zero ? t : fmaf(bc, c[off], t);
+        }
+    }
+}
+
+// Complex C: (re, im) is alpha-free AB for this element (im == 0 in case 1c).
+template <class T, class W>
+__device__ __forceinline__ void cupdate(const GemmArgs &g, W *c2, W re, W im, W ar, W ai) {
+    const W tr = fma(ar, re, -(ai * im));
+    const W ti = fma(ar, im, ai * re);
+    if (g.beta_zero) {
+        c2[0] = tr;
+        c2[1] = ti;
+    } else {
+        const W br = (W)g.beta_re, bi = (W)g.beta_im;
+        const W cr = c2[0], ci = c2[1];
+        c2[0] = fma(br, cr, fma(-bi, ci, tr));
+        c2[1] = fma(br, ci, fma(bi, cr, ti));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_t j, T re, T im) {
+    if (i >= g.m || j >= g.n) return;
+    const int64_t off = 2 * (i + j * g.ldc);
+    const T ar = (T)g.alpha_re, ai = (T)g.alpha_im;
+    if (g.c_dbl) {
+        double *c = (double *)g.C + off;
+        // beta is already double (C's precision); product in double.
+        cupdate<T, double>(g, c, (double)re, (double)im, (double)ar, (double)ai);
+    } else if constexpr (sizeof(T) == 8) {
+        // computation in double, C single: beta cast to single, update in double
+        float *c = (float *)g.C + off;
+        const double br = (double)(float)g.beta_re, bi = (double)(float)g.beta_im;
+        const double tr = fma(ar, re, -(ai * im));
+        const double ti = fma(ar, im, ai * re);
+        double rr = tr, ri = ti;
+        if (!g.beta_zero) {
+            const double cr = c[0], ci = c[1];
+            rr = fma(br, cr, fma(-bi, ci, tr));
+            ri = fma(br, ci, fma(bi, cr, ti));
+        }
+        c[0] = (float)rr;
+        c[1] = (float)ri;
+    } else {
+        float *c = (float *)g.C + off;
+        cupdate<T, float>(g, c, re, im, ar, ai);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The product kernel
+// ---------------------------------------------------------------------------
+// Scheduling hints for the compiler's instruction scheduler (masks of
+// __builtin_amdgcn_sched_group_barrier): keep the matrix core fed by placing
+// LDS and vector work between MFMAs.
+constexpr int SG_VALU = 0x002, SG_MFMA = 0x008, SG_DSR = 0x100, SG_DSW = 0x200;
+
+template <class T, int CS, bool FAST, bool AD, bool BD>
+__global__ __launch_bounds__(NT, 2) void md_gemm_kernel(GemmArgs g) {
+    typedef TileCfg<T> C;
+    typedef Stage<T, CS, true, FAST, AD> SA;
+    typedef Stage<T, CS, false, FAST, BD> SB;
+    typedef typename AccT<T>::type acc_t;
+    static_assert(SA::TK == SB::TK, "A and B disagree on the k lowering");
+    constexpr bool MDBL = SA::MN2, NDBL = SB::MN2;
+    constexpr bool CCPLX = (CS == MD_CASE_1C || CS == MD_CASE_2AC || CS == MD_CASE_2BC || CS == MD_CASE_3);
+    constexpr int S = C::BK / 4;  // MFMA k-steps per LDS tile
+
+    __shared__ T sA[2][C::BK * SA::LDW];
+    __shared__ T sB[2][C::BK * SB::LDW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
+    int tm, tn;
+    map_tile(blockIdx.x, gridDim.x, g.tiles_m, g.tiles_n, &tm, &tn);
+    const int64_t mn0a = (int64_t)tm * SA::TMN, mn0b = (int64_t)tn * SB::TMN;
+    const int nk = (int)((g.k + SA::TK - 1) / SA::TK);
+
+    acc_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    SA la(g, tid, mn0a);
+    SB lb(g, tid, mn0b);
+    T fa[2][4], fb[2][4];
+    const int fofs_a = (lane >> 4) * SA::LDW + wm0 + (lane & 15);
+    const int fofs_b = (lane >> 4) * SB::LDW + wn0 + (lane & 15);
+
+    auto read_frags = [&](const T *pa, const T *pb, int s, int slot) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fa[slot][i] = pa[s * 4 * SA::LDW + fofs_a + i * 16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fb[slot][i] = pb[s * 4 * SB::LDW + fofs_b + i * 16];
+    };
+    auto mfmas = [&](int slot) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(fb[slot][b], fa[slot][a], acc[a][b]);
+    };
+    // One LDS tile: S k-steps of 16 MFMAs.  Fragments of step s+1 are read
+    // while step s multiplies; with STORE the next tile's staged registers are
+    // converted and written to the other LDS buffer during the last step.
+    auto tile = [&](int cur, auto store_tag) {
+        constexpr bool STORE = decltype(store_tag)::value;
+        const T *pa = sA[cur];
+        const T *pb = sB[cur];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s + 1 < S) read_frags(pa, pb, s + 1, (s + 1) & 1);
+            if (STORE && s == S - 1) {
+                la.store(sA[cur ^ 1]);
+                lb.store(sB[cur ^ 1]);
+            }
+            mfmas(s & 1);
+            if (s + 1 < S) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(SG_DSR, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(SG_MFMA, 8, 0);
+            } else if (STORE) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(SG_VALU, 6, 0);
+                    __builtin_amdgcn_sched_group_barrier(SG_DSW, 2, 0);
+                }
+            }
+        }
+    };
+
+    la.load(0);
+    lb.load(0);
+    la.store(sA[0]);
+    lb.store(sB[0]);
+    __syncthreads();
+    if (nk > 1) {
+        la.load(1);
+        lb.load(1);
+    }
+    read_frags(sA[0], sB[0], 0, 0);
+    int t = 0;
+    for (; t + 1 < nk; ++t) {
+        const int cur = t & 1;
+        tile(cur, std::true_type{});
+        __syncthreads();
+        if (t + 2 < nk) {
+            la.load(t + 2);
+            lb.load(t + 2);
+        }
+        read_frags(sA[cur ^ 1], sB[cur ^ 1], 0, 0);
+    }
+    tile(t & 1, std::false_type{});
+
+    // Epilogue.  acc[a][b] item v is C'(row m = wm0 + 16a + (lane & 15),
+    //                                   col n = wn0 + 16b + acc_row(lane, v)).
+    const int ml = lane & 15;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int nl = acc_row<T>(lane, v);
+            if constexpr (MDBL) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
+                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                    update_cplx<T>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
+                }
+            } else if constexpr (NDBL) {
+                if ((b & 1) == 0) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
+                        const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
+                        update_cplx<T>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
+                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                    if constexpr (CCPLX) update_cplx<T>(g, i, j, acc[a][b][v], (T)0);
+                    else update_real<T>(g, i, j, acc[a][b][v]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace md

@@ -85,10 +85,13 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     // length (in real components) is a multiple of four so that no chunk of
     // four components straddles the end of a column.
     const int wa = dt_cplx(dta) ? 2 : 1, wb = dt_cplx(dtb) ? 2 : 1;
+    // The fast kernels address a tile with 32-bit offsets from its origin:
+    // 128 columns of the operand must span less than 2 GiB.
+    const int64_t max_ld = ((int64_t)1 << 31) / (128 * 16) - 64;
     g.a_vec = ((uintptr_t)A % 16 == 0) && ((lda * dt_bytes(dta)) % 16 == 0) &&
-              (((ta == 0 ? m : k) * wa) % 4 == 0);
+              (((ta == 0 ? m : k) * wa) % 4 == 0) && lda < max_ld;
     g.b_vec = ((uintptr_t)B % 16 == 0) && ((ldb * dt_bytes(dtb)) % 16 == 0) &&
-              (((tb == 0 ? k : n) * wb) % 4 == 0);
+              (((tb == 0 ? k : n) * wb) % 4 == 0) && ldb < max_ld;
     g.alpha_re = are; g.alpha_im = aim;
     g.beta_re = bre; g.beta_im = bim;
     g.beta_zero = (bre == 0.0 && bim == 0.0);
@@ -146,7 +149,7 @@ int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
         tile_shape(d.prec, d.cs, &bm, &bn, &bk);
         out->tile_m = bm; out->tile_n = bn; out->tile_k = bk;
         out->workgroups = (int64_t)d.g.tiles_m * d.g.tiles_n;
-        snprintf(out->kernel, sizeof(out->kernel), "%s", kernel_name(d.prec, d.cs));
+        kernel_name(d.prec, d.cs, d.g, out->kernel, (int)sizeof(out->kernel));
     } else if (d.quick == 2) {
         snprintf(out->kernel, sizeof(out->kernel), "md_scale_kernel");
     }

@@ -1,0 +1,97 @@
+// mdgemm_launch.hip -- host-side dispatch to the product kernels, the
+// beta-scaling kernel used by the quick returns, and tile/kernel metadata.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+
+#include "md_internal.h"
+
+namespace md {
+
+#define MD_DECL_PARTS(t)                                                       \
+    void launch_part_##t##_0(const GemmArgs &, hipStream_t, unsigned);         \
+    void launch_part_##t##_1(const GemmArgs &, hipStream_t, unsigned);         \
+    void launch_part_##t##_2(const GemmArgs &, hipStream_t, unsigned);         \
+    void launch_part_##t##_3(const GemmArgs &, hipStream_t, unsigned);         \
+    void launch_part_##t##_4(const GemmArgs &, hipStream_t, unsigned);         \
+    void launch_part_##t##_5(const GemmArgs &, hipStream_t, unsigned);         \
+    void launch_part_##t##_6(const GemmArgs &, hipStream_t, unsigned);         \
+    void launch_part_##t##_7(const GemmArgs &, hipStream_t, unsigned);
+MD_DECL_PARTS(0)
+MD_DECL_PARTS(1)
+
+typedef void (*part_fn)(const GemmArgs &, hipStream_t, unsigned);
+static const part_fn kParts[2][8] = {
+    {launch_part_0_0, launch_part_0_1, launch_part_0_2, launch_part_0_3,
+     launch_part_0_4, launch_part_0_5, launch_part_0_6, launch_part_0_7},
+    {launch_part_1_0, launch_part_1_1, launch_part_1_2, launch_part_1_3,
+     launch_part_1_4, launch_part_1_5, launch_part_1_6, launch_part_1_7}};
+
+// C := beta*C (alpha == 0 or k == 0).  beta == 0 writes zeros without reading C.
+__global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
+    const int64_t total = g.m * g.n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t % g.m, j = t / g.m;
+        const int64_t off = i + j * g.ldc;
+        if (g.c_cplx) {
+            if (g.c_dbl) {
+                double *c = (double *)g.C + 2 * off;
+                if (g.beta_zero) { c[0] = 0.0; c[1] = 0.0; }
+                else {
+                    const double br = g.beta_re, bi = g.beta_im, cr = c[0], ci = c[1];
+                    c[0] = fma(br, cr, -(bi * ci));
+                    c[1] = fma(br, ci, bi * cr);
+                }
+            } else {
+                float *c = (float *)g.C + 2 * off;
+                if (g.beta_zero) { c[0] = 0.0f; c[1] = 0.0f; }
+                else {
+                    const float br = (float)g.beta_re, bi = (float)g.beta_im, cr = c[0], ci = c[1];
+                    c[0] = fmaf(br, cr, -(bi * ci));
+                    c[1] = fmaf(br, ci, bi * cr);
+                }
+            }
+        } else if (g.c_dbl) {
+            double *c = (double *)g.C;
+            c[off] = g.beta_zero ? 0.0 : g.beta_re * c[off];
+        } else {
+            float *c = (float *)g.C;
+            c[off] = g.beta_zero ? 0.0f : (float)g.beta_re * c[off];
+        }
+    }
+}
+
+
+int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg) {
+    const int64_t n = (int64_t)a.tiles_m * a.tiles_n;
+    if (wg) *wg = n;
+    if (n <= 0) return 0;
+    if ((prec != PREC_D && prec != PREC_S) || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
+    kParts[prec == PREC_D ? 1 : 0][cs](a, (hipStream_t)stream, (unsigned)n);
+    return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
+}
+
+int launch_scale(const GemmArgs &a, void *stream) {
+    const int64_t total = a.m * a.n;
+    if (total <= 0) return 0;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(md_scale_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
+}
+
+void tile_shape(int prec, int cs, int *bm, int *bn, int *bk) {
+    (void)cs;
+    *bm = 128;
+    *bn = 128;
+    *bk = prec == PREC_D ? 16 : 32;
+}
+
+void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len) {
+    static const char *cases[8] = {"0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3"};
+    snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c", prec == PREC_D ? "f64" : "f32",
+             (cs >= 0 && cs < 8) ? cases[cs] : "?", (a.a_vec && a.b_vec) ? "fast" : "generic",
+             a.a_dbl ? 'd' : 's', a.b_dbl ? 'd' : 's');
+}
+
+}  // namespace md
