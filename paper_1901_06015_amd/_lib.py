@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmdgemm.so")
+# MDGEMM_LIBRARY may name another build of the same library (for example one
+# compiled with different tuning knobs).
+LIB_PATH = os.environ.get("MDGEMM_LIBRARY", os.path.join(HERE, "libmdgemm.so"))
 
 MD_S, MD_D, MD_C, MD_Z = 0, 1, 2, 3
 MD_COMP_DEFAULT, MD_COMP_S, MD_COMP_D, MD_COMP_S_BF16X3 = -1, 0, 1, 2

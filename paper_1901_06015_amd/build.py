@@ -35,10 +35,11 @@ SOURCES = [("mdgemm_kernels.hip", ["-DMD_KT=%d" % t, "-DMD_KCASE=%d" % c], "k_%d
 ]
 
 
-def _compile(entry):
+def _compile(entry, extra=(), build_dir=BUILD):
     src, defs, objname = entry
+    defs = list(defs) + list(extra)
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, objname)
+    obj = os.path.join(build_dir, objname)
     if src.endswith(".hip"):
         cmd = [HIPCC] + HIP_FLAGS + defs + ["-c", path, "-o", obj]
     else:
@@ -49,20 +50,22 @@ def _compile(entry):
     return obj
 
 
-def build(verbose=True):
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=True, defines=(), out=OUT, build_dir=BUILD):
+    """Compile and link.  `defines` (e.g. ["-DMD_OCC=1"]) set the tuning knobs
+    of md_tile.h; `out` and `build_dir` place a variant build elsewhere."""
+    os.makedirs(build_dir, exist_ok=True)
     srcs = [e for e in SOURCES if os.path.exists(os.path.join(CSRC, e[0]))]
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(int(os.environ.get('MAX_JOBS', '8')), len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda e: _compile(e, defines, build_dir), srcs))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), res.stderr))
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

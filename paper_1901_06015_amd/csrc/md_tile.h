@@ -1,50 +1,58 @@
 // md_tile.h -- device side of libmdgemm for gfx950 (CDNA4): the product kernel
 // template, instantiated by mdgemm_kernels.hip.
 //
-// One templated kernel per (computation precision, domain case).  Each
-// workgroup owns a tile of the real product C' += A' B' that its case lowers
-// to (md_internal.h, Figure "mixeddom"):
+// Each workgroup owns a tile of the real product C' += A' B' that its domain
+// case lowers to (md_internal.h, Figure "mixeddom"):
 //
 //   1. cast-on-pack: A and B tiles are read from HBM in their storage type
-//      with 16-byte vector loads, converted to the computation type in
-//      registers (float -> double exact, double -> float round-to-nearest-even,
-//      the typecasting pack of Section 4) and written to LDS already in the
-//      layout of the real product: complex elements are split into their
-//      parts, the parts that cannot reach C are dropped, conjugation flips a
-//      sign, and case 3 writes A in the 1e arrangement of Eq. 1mc (each complex
-//      element becomes the real 2x2 block [re -im; im re]) while B keeps the
-//      1r arrangement (re, im interleaved along k);
+//      with 16-byte loads, converted to the computation type in registers
+//      (float -> double exact, double -> float round-to-nearest-even: the
+//      typecasting pack of Section 4) and written to LDS already in the layout
+//      of the real product: complex elements are split into their parts, parts
+//      that cannot reach C are dropped, conjugation flips a sign, and case 3
+//      writes A in the 1e arrangement of Eq. 1mc (each complex element becomes
+//      the real 2x2 block [re -im; im re]) while B keeps the 1r arrangement
+//      (re, im interleaved along k);
 //   2. a double-buffered k loop of real MFMA (v_mfma_f64_16x16x4f64 or
-//      v_mfma_f32_16x16x4f32) over the LDS tiles: the global loads of tile t+1
-//      are in flight while tile t is multiplied;
+//      v_mfma_f32_16x16x4f32) over the LDS tiles: the global loads of tile t+2
+//      are in flight while tile t multiplies, the fragments of the next k group
+//      are read while the current one multiplies, and the LDS writes of tile
+//      t+1 are interleaved with the last MFMAs of tile t;
 //   3. an epilogue that applies alpha (cast to the computation precision) and
 //      beta (cast to C's storage precision), forms beta*C + alpha*AB in the
 //      wider of the computation and C precisions, and rounds once to C's
 //      storage type (Sections 4.1.3 and 6.1).
 //
+// LDS layout follows each operand's orientation in HBM so that the staging
+// writes are 16-byte vectors without bank conflicts: an operand contiguous
+// along m (or n) is kept as [k][mn], one contiguous along k as [mn][k].
 // The MFMA is issued with B' as its first operand so that the accumulator
 // lanes run along m: stores to column-major C are then contiguous.
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
 
-#pragma once
 #include "md_internal.h"
 
 namespace md {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 constexpr int NT = 256;  // threads per workgroup: 4 waves of 64
 constexpr int G = 16;    // MFMA block edge (16x16 output blocks)
 
+// Workgroup tile of the real product, k depth of one LDS tile, and the LDS
+// row padding of each layout (chosen so that fragment reads and staging
+// writes hit distinct banks).
 template <class T> struct TileCfg;
 template <> struct TileCfg<double> {
-    static constexpr int BM = 128, BN = 128, BK = 16, PAD = 16;
+    static constexpr int BM = 128, BN = 128, BK = 16, PADW = 8, PADK = 2;
 };
 template <> struct TileCfg<float> {
-    static constexpr int BM = 128, BN = 128, BK = 32, PAD = 16;
+    static constexpr int BM = 128, BN = 128, BK = 32, PADW = 4, PADK = 4;
 };
 
 template <class T> struct AccT;
@@ -64,6 +72,15 @@ __device__ __forceinline__ v4f mfma16(float x, float y, v4f c) {
 template <class T> __device__ __forceinline__ int acc_row(int lane, int v);
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int v) { return 4 * v + (lane >> 4); }
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+
+// LDS layout of one operand tile: BMN (m or n) x BK (k) elements of T.
+template <class T, bool MNC, int BMN>
+struct Lay {
+    typedef TileCfg<T> C;
+    static constexpr int LD = MNC ? BMN + C::PADW : C::BK + C::PADK;
+    static constexpr int SIZE = (MNC ? C::BK : BMN) * LD;
+    __device__ __forceinline__ static int at(int kk, int mm) { return MNC ? kk * LD + mm : mm * LD + kk; }
+};
 
 // ---------------------------------------------------------------------------
 // Operand staging (cast-on-pack)
@@ -93,7 +110,12 @@ template <int CS, bool IS_A> __host__ __device__ constexpr int mode_of() {
 // complex element land in the same lane of the same MFMA block pair.
 __device__ __forceinline__ int split_pos(int mm, int q) { return (((mm >> 4) << 1) + q) * G + (mm & 15); }
 
-template <class T, int CS, bool IS_A, bool FAST, bool SDBL>
+// FAST: aligned operand, 16-byte buffer loads, LDS layout = orientation MNC
+//       (true: contiguous along m/n in HBM).
+// !FAST: any alignment / leading dimension; the orientation comes from the
+//       trans argument at run time, components are loaded one by one and the
+//       LDS layout is [k][mn] (MNC must be true).
+template <class T, int CS, bool IS_A, bool FAST, bool SDBL, bool MNC>
 struct Stage {
     typedef TileCfg<T> C;
     static constexpr int MODE = mode_of<CS, IS_A>();
@@ -101,26 +123,25 @@ struct Stage {
     static constexpr bool MN2 = (MODE == M_MNINT || MODE == M_ONEE);
     static constexpr bool K2 = (MODE == M_KINT || MODE == M_ONEE);
     static constexpr int BMN = IS_A ? C::BM : C::BN;
+    typedef Lay<T, MNC, BMN> L;
     static constexpr int TMN = BMN / (MN2 ? 2 : 1);  // stored m (or n) extent of a tile
     static constexpr int TK = C::BK / (K2 ? 2 : 1);   // stored k extent of a tile
     static constexpr int CHUNKS = TMN * TK * W / 4;   // 4 components per chunk
     static constexpr int PER = CHUNKS / NT;
-    static constexpr int LDW = BMN + C::PAD;          // LDS row stride (elements)
     static constexpr int ESZ = SDBL ? 8 : 4;          // bytes per stored component
     static constexpr int NV = SDBL ? 2 : 1;           // 16-byte vectors per chunk
-    // chunks per stored column of a tile, for either layout (powers of two)
     static constexpr int CPC_MN = TMN * W / 4, CPC_K = TK * W / 4;
     // Sign applied to Im when it is placed at an odd k' row: -Im(A) in case 2ab
     // realises Re(AB) = ArBr - AiBi; B's Im enters positively.
     static constexpr bool KNEG = IS_A;
+    static_assert(FAST || MNC, "the generic path stages into the [k][mn] layout");
     static_assert(CHUNKS % NT == 0, "tile does not split evenly over the workgroup");
     static_assert((TMN * W) % 4 == 0 && (TK * W) % 4 == 0, "chunks straddle columns");
     static_assert((CPC_MN & (CPC_MN - 1)) == 0 && (CPC_K & (CPC_K - 1)) == 0 && CPC_MN <= NT && CPC_K <= NT,
                   "chunk grid must be a power of two no wider than the workgroup");
 
-    // Registers holding one tile's loads until they are converted.
     struct Chunk { uint4 v[NV]; };
-    Chunk raw[PER];
+    Chunk raw[PER];  // one tile's loads, held until converted
 
     const char *base;
     int64_t ld, MN, K, mn0;
@@ -132,7 +153,7 @@ struct Stage {
 
     __device__ __forceinline__ Stage(const GemmArgs &g, int tid, int64_t mn0_) {
         const int tr = IS_A ? g.ta : g.tb;
-        mn_contig = IS_A ? (tr == 0) : (tr != 0);
+        mn_contig = FAST ? MNC : (IS_A ? (tr == 0) : (tr != 0));
         conj = (tr == 2);
         ld = IS_A ? g.lda : g.ldb;
         MN = IS_A ? g.m : g.n;
@@ -152,7 +173,7 @@ struct Stage {
     // beyond the resource's range and reads as zero, with no branch.
     __device__ __forceinline__ void load_fast(int t) {
         const int64_t k0 = (int64_t)t * TK;
-        const int64_t base_off = (mn_contig ? (k0 * ld + mn0) : (mn0 * ld + k0)) * W * ESZ;
+        const int64_t base_off = (MNC ? (k0 * ld + mn0) : (mn0 * ld + k0)) * W * ESZ;
         const int64_t rem = total_bytes - base_off;
         const int nrec = rem > 0x7fffffffLL ? 0x7fffffff : (rem < 0 ? 0 : (int)rem);
         __amdgpu_buffer_rsrc_t rs =
@@ -166,9 +187,8 @@ struct Stage {
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;
-            // element index along m/n and along k of this chunk's first element
-            const int e_mn = mn_contig ? epos : col;
-            const int e_k = mn_contig ? col : epos;
+            const int e_mn = MNC ? epos : col;
+            const int e_k = MNC ? col : epos;
             const bool ok = (e_mn < mlim) && (e_k < klim);
             const uint32_t off = ok ? (uint32_t)col * col_bytes + (uint32_t)(pos * 4 * ESZ) : 0x80000000u;
 #pragma unroll
@@ -179,8 +199,7 @@ struct Stage {
         }
     }
 
-    // Generic path: any alignment and leading dimension; components are
-    // loaded one by one and anything outside the matrix reads as zero.
+    // Generic path: components loaded one by one; outside the matrix reads zero.
     __device__ __forceinline__ void load_generic(int t) {
         const int64_t k0 = (int64_t)t * TK;
         const int64_t rows_st = mn_contig ? MN : K, cols_st = mn_contig ? K : MN;
@@ -218,8 +237,7 @@ struct Stage {
         else load_generic(t);
     }
 
-    // Component q of a chunk converted to the computation type (the
-    // typecasting pack: float -> double exact, double -> float nearest-even).
+    // Component q of a chunk converted to the computation type.
     __device__ __forceinline__ static T component(const Chunk &x, int q) {
         if constexpr (SDBL) {
             const uint4 h = x.v[q >> 1];
@@ -233,33 +251,33 @@ struct Stage {
         }
     }
 
+    // Place part `part` (0 Re, 1 Im) of stored element (mm, kk) of the tile.
     __device__ __forceinline__ static void emit(T *lds, int mm, int kk, int part, T v, bool conj) {
         if constexpr (MODE == M_PLAIN) {
-            lds[kk * LDW + mm] = v;
+            lds[L::at(kk, mm)] = v;
         } else if constexpr (MODE == M_REONLY) {
-            if (part == 0) lds[kk * LDW + mm] = v;
+            if (part == 0) lds[L::at(kk, mm)] = v;
         } else {
             const T vi = conj ? -v : v;
             if constexpr (MODE == M_KINT) {
-                if (part == 0) lds[(2 * kk) * LDW + mm] = v;
-                else lds[(2 * kk + 1) * LDW + mm] = KNEG ? -vi : vi;
+                if (part == 0) lds[L::at(2 * kk, mm)] = v;
+                else lds[L::at(2 * kk + 1, mm)] = KNEG ? -vi : vi;
             } else if constexpr (MODE == M_MNINT) {
-                if (part == 0) lds[kk * LDW + split_pos(mm, 0)] = v;
-                else lds[kk * LDW + split_pos(mm, 1)] = vi;
+                if (part == 0) lds[L::at(kk, split_pos(mm, 0))] = v;
+                else lds[L::at(kk, split_pos(mm, 1))] = vi;
             } else {  // M_ONEE: [re -im; im re] per complex element (Eq. 1mc)
                 if (part == 0) {
-                    lds[(2 * kk) * LDW + split_pos(mm, 0)] = v;
-                    lds[(2 * kk + 1) * LDW + split_pos(mm, 1)] = v;
+                    lds[L::at(2 * kk, split_pos(mm, 0))] = v;
+                    lds[L::at(2 * kk + 1, split_pos(mm, 1))] = v;
                 } else {
-                    lds[(2 * kk) * LDW + split_pos(mm, 1)] = vi;
-                    lds[(2 * kk + 1) * LDW + split_pos(mm, 0)] = -vi;
+                    lds[L::at(2 * kk, split_pos(mm, 1))] = vi;
+                    lds[L::at(2 * kk + 1, split_pos(mm, 0))] = -vi;
                 }
             }
         }
     }
 
-    // Convert the staged registers and write them to one LDS buffer.  `part`
-    // (Re/Im) is known at compile time; the layout choice is a select.
+    // Convert the staged registers and write them to one LDS buffer.
     __device__ __forceinline__ void store(T *lds) const {
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
@@ -269,9 +287,14 @@ struct Stage {
                 const T v = component(raw[c], q);
                 const int e = pos * (4 / W) + q / W;
                 const int part = q % W;
-                const int mm = mn_contig ? e : col;
-                const int kk = mn_contig ? col : e;
-                emit(lds, mm, kk, part, v, conj);
+                if constexpr (FAST) {
+                    if constexpr (MNC) emit(lds, e, col, part, v, conj);
+                    else emit(lds, col, e, part, v, conj);
+                } else {
+                    const int mm = mn_contig ? e : col;
+                    const int kk = mn_contig ? col : e;
+                    emit(lds, mm, kk, part, v, conj);
+                }
             }
         }
     }
@@ -372,24 +395,70 @@ __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_
 // ---------------------------------------------------------------------------
 // The product kernel
 // ---------------------------------------------------------------------------
-// Scheduling hints for the compiler's instruction scheduler (masks of
-// __builtin_amdgcn_sched_group_barrier): keep the matrix core fed by placing
-// LDS and vector work between MFMAs.
+// Masks of __builtin_amdgcn_sched_group_barrier: keep the matrix core fed by
+// placing LDS and vector work between MFMAs.
 constexpr int SG_VALU = 0x002, SG_MFMA = 0x008, SG_DSR = 0x100, SG_DSW = 0x200;
 
-template <class T, int CS, bool FAST, bool AD, bool BD>
-__global__ __launch_bounds__(NT, 2) void md_gemm_kernel(GemmArgs g) {
+// MFMA fragments.  Within a "k group" of KV = 16/sizeof(T) consecutive
+// k-steps, lane group g = lane >> 4 of step j multiplies k' = 4*KV*grp +
+// KV*g + j -- the same mapping for A' and B' -- so an operand kept as [mn][k]
+// delivers a whole group with one 16-byte LDS read per block, while an operand
+// kept as [k][mn] is read one element per block and step.  Two buffers: the
+// fragments of step s+1 are read while step s multiplies.
+template <class T, bool MNC, int BMN>
+struct Frag {
+    typedef Lay<T, MNC, BMN> L;
+    static constexpr int KV = 16 / (int)sizeof(T);
+    static constexpr int NE = MNC ? 1 : KV;
+    T f[2][4][NE];
+    // Read what step s needs (for [mn][k]: its whole group, at the group's first step).
+    __device__ __forceinline__ void read(const T *lds, int s, int lane, int w0) {
+        const int g = lane >> 4, r = lane & 15;
+        if constexpr (MNC) {
+            const int row = (s / KV) * 4 * KV + KV * g + (s % KV);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[s & 1][i][0] = lds[L::at(row, w0 + 16 * i + r)];
+        } else {
+            if (s % KV != 0) return;
+            typedef T vec_t __attribute__((ext_vector_type(KV)));
+            const int grp = s / KV;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const vec_t x = *(const vec_t *)&lds[L::at(4 * KV * grp + KV * g, w0 + 16 * i + r)];
+#pragma unroll
+                for (int j = 0; j < KV; ++j) f[grp & 1][i][j] = x[j];
+            }
+        }
+    }
+    __device__ __forceinline__ T get(int s, int i) const {
+        if constexpr (MNC) return f[s & 1][i][0];
+        else return f[(s / KV) & 1][i][s % KV];
+    }
+};
+
+// Build-time tuning knobs: MD_OCC waves per SIMD the kernels are compiled for
+// (2: two workgroups per CU share each SIMD, 256 registers per lane; 1: one
+// workgroup per CU, 512 registers per lane); MD_SCHED=0 leaves instruction
+// interleaving to the compiler.
+#ifndef MD_OCC
+#define MD_OCC 2
+#endif
+#ifndef MD_SCHED
+#define MD_SCHED 1
+#endif
+
+template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC>
+__global__ __launch_bounds__(NT, MD_OCC) void md_gemm_kernel(GemmArgs g) {
     typedef TileCfg<T> C;
-    typedef Stage<T, CS, true, FAST, AD> SA;
-    typedef Stage<T, CS, false, FAST, BD> SB;
+    typedef Stage<T, CS, true, FAST, AD, AMNC> SA;
+    typedef Stage<T, CS, false, FAST, BD, BMNC> SB;
     typedef typename AccT<T>::type acc_t;
     static_assert(SA::TK == SB::TK, "A and B disagree on the k lowering");
     constexpr bool MDBL = SA::MN2, NDBL = SB::MN2;
     constexpr bool CCPLX = (CS == MD_CASE_1C || CS == MD_CASE_2AC || CS == MD_CASE_2BC || CS == MD_CASE_3);
-    constexpr int S = C::BK / 4;  // MFMA k-steps per LDS tile
 
-    __shared__ T sA[2][C::BK * SA::LDW];
-    __shared__ T sB[2][C::BK * SB::LDW];
+    __shared__ __attribute__((aligned(16))) T sA[2][SA::L::SIZE];
+    __shared__ __attribute__((aligned(16))) T sB[2][SB::L::SIZE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
@@ -406,50 +475,43 @@ __global__ __launch_bounds__(NT, 2) void md_gemm_kernel(GemmArgs g) {
 
     SA la(g, tid, mn0a);
     SB lb(g, tid, mn0b);
-    T fa[2][4], fb[2][4];
-    const int fofs_a = (lane >> 4) * SA::LDW + wm0 + (lane & 15);
-    const int fofs_b = (lane >> 4) * SB::LDW + wn0 + (lane & 15);
+    Frag<T, AMNC, C::BM> fa;
+    Frag<T, BMNC, C::BN> fb;
+    constexpr int S = C::BK / 4;  // MFMA k-steps per LDS tile
 
-    auto read_frags = [&](const T *pa, const T *pb, int s, int slot) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) fa[slot][i] = pa[s * 4 * SA::LDW + fofs_a + i * 16];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) fb[slot][i] = pb[s * 4 * SB::LDW + fofs_b + i * 16];
-    };
-    auto mfmas = [&](int slot) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(fb[slot][b], fa[slot][a], acc[a][b]);
-    };
-    // One LDS tile: S k-steps of 16 MFMAs.  Fragments of step s+1 are read
-    // while step s multiplies; with STORE the next tile's staged registers are
-    // converted and written to the other LDS buffer during the last step.
+    // One LDS tile of S k-steps of 16 MFMAs.  The fragments of step s+1 are
+    // read while step s multiplies; with STORE the next tile's staged
+    // registers are converted and written to the other LDS buffer during the
+    // last step.
     auto tile = [&](int cur, auto store_tag) {
         constexpr bool STORE = decltype(store_tag)::value;
-        const T *pa = sA[cur];
-        const T *pb = sB[cur];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            if (s + 1 < S) read_frags(pa, pb, s + 1, (s + 1) & 1);
+            if (s + 1 < S) {
+                fa.read(sA[cur], s + 1, lane, wm0);
+                fb.read(sB[cur], s + 1, lane, wn0);
+            }
             if (STORE && s == S - 1) {
                 la.store(sA[cur ^ 1]);
                 lb.store(sB[cur ^ 1]);
             }
-            mfmas(s & 1);
-            if (s + 1 < S) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(fb.get(s, b), fa.get(s, a), acc[a][b]);
+            if (MD_SCHED && s + 1 < S) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
                     __builtin_amdgcn_sched_group_barrier(SG_DSR, 1, 0);
                 }
                 __builtin_amdgcn_sched_group_barrier(SG_MFMA, 8, 0);
-            } else if (STORE) {
+            } else if (MD_SCHED && STORE) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(SG_VALU, 6, 0);
-                    __builtin_amdgcn_sched_group_barrier(SG_DSW, 2, 0);
+                    __builtin_amdgcn_sched_group_barrier(SG_VALU, 4, 0);
+                    __builtin_amdgcn_sched_group_barrier(SG_DSW, 1, 0);
                 }
             }
         }
@@ -464,7 +526,8 @@ __global__ __launch_bounds__(NT, 2) void md_gemm_kernel(GemmArgs g) {
         la.load(1);
         lb.load(1);
     }
-    read_frags(sA[0], sB[0], 0, 0);
+    fa.read(sA[0], 0, lane, wm0);
+    fb.read(sB[0], 0, lane, wn0);
     int t = 0;
     for (; t + 1 < nk; ++t) {
         const int cur = t & 1;
@@ -474,7 +537,8 @@ __global__ __launch_bounds__(NT, 2) void md_gemm_kernel(GemmArgs g) {
             la.load(t + 2);
             lb.load(t + 2);
         }
-        read_frags(sA[cur ^ 1], sB[cur ^ 1], 0, 0);
+        fa.read(sA[cur ^ 1], 0, lane, wm0);
+        fb.read(sB[cur ^ 1], 0, lane, wn0);
     }
     tile(t & 1, std::false_type{});
 

@@ -2,8 +2,9 @@
 //
 // Compiled once per (computation precision, domain case) with
 // -DMD_KT=<0 single | 1 double> and -DMD_KCASE=<md_case> so that the 128
-// variants (2 computation precisions x 8 cases x 2 load paths x 4 storage
-// precisions of A and B) build in parallel.
+// variants (2 computation precisions x 8 cases x 4 storage precisions of A and
+// B x 5 load paths: the fast path for each of the 4 operand orientations and
+// the generic path) build in parallel.
 #include "md_tile.h"
 
 #ifndef MD_KT
@@ -21,21 +22,34 @@ typedef float KT;
 typedef double KT;
 #endif
 
-template <int CS, bool FAST>
+template <int CS, bool FAST, bool AMNC, bool BMNC>
 static void launch_v(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     if (a.a_dbl) {
-        if (a.b_dbl) hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, true, true>), dim3(nwg), dim3(NT), 0, s, a);
-        else hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, true, false>), dim3(nwg), dim3(NT), 0, s, a);
+        if (a.b_dbl) hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, true, true, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, true, false, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
     } else {
-        if (a.b_dbl) hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, false, true>), dim3(nwg), dim3(NT), 0, s, a);
-        else hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, false, false>), dim3(nwg), dim3(NT), 0, s, a);
+        if (a.b_dbl) hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, false, true, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, false, false, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
     }
 }
 
+// The fast kernels take the operands' orientation (A contiguous along m for
+// 'N', B contiguous along n for 'T'/'C') as template parameters; the generic
+// kernels read it from the arguments.
 template <int CS>
 static void launch_c(const GemmArgs &a, hipStream_t s, unsigned nwg) {
-    if (a.a_vec && a.b_vec) launch_v<CS, true>(a, s, nwg);
-    else launch_v<CS, false>(a, s, nwg);
+    if (a.a_vec && a.b_vec) {
+        const bool am = a.ta == 0, bm = a.tb != 0;
+        if (am) {
+            if (bm) launch_v<CS, true, true, true>(a, s, nwg);
+            else launch_v<CS, true, true, false>(a, s, nwg);
+        } else {
+            if (bm) launch_v<CS, true, false, true>(a, s, nwg);
+            else launch_v<CS, true, false, false>(a, s, nwg);
+        }
+    } else {
+        launch_v<CS, false, true, true>(a, s, nwg);
+    }
 }
 
 #define MD_PART_NAME2(t, c) launch_part_##t##_##c
