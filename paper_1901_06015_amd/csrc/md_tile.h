@@ -126,22 +126,21 @@ struct Stage {
     typedef Lay<T, MNC, BMN> L;
     static constexpr int TMN = BMN / (MN2 ? 2 : 1);  // stored m (or n) extent of a tile
     static constexpr int TK = C::BK / (K2 ? 2 : 1);   // stored k extent of a tile
-    static constexpr int CHUNKS = TMN * TK * W / 4;   // 4 components per chunk
-    static constexpr int PER = CHUNKS / NT;
     static constexpr int ESZ = SDBL ? 8 : 4;          // bytes per stored component
-    static constexpr int NV = SDBL ? 2 : 1;           // 16-byte vectors per chunk
-    static constexpr int CPC_MN = TMN * W / 4, CPC_K = TK * W / 4;
+    static constexpr int CW = 16 / ESZ;               // components per chunk (one 16-byte load)
+    static constexpr int CHUNKS = TMN * TK * W / CW;
+    static constexpr int PER = CHUNKS / NT;
+    static constexpr int CPC_MN = TMN * W / CW, CPC_K = TK * W / CW;
     // Sign applied to Im when it is placed at an odd k' row: -Im(A) in case 2ab
     // realises Re(AB) = ArBr - AiBi; B's Im enters positively.
     static constexpr bool KNEG = IS_A;
     static_assert(FAST || MNC, "the generic path stages into the [k][mn] layout");
     static_assert(CHUNKS % NT == 0, "tile does not split evenly over the workgroup");
-    static_assert((TMN * W) % 4 == 0 && (TK * W) % 4 == 0, "chunks straddle columns");
+    static_assert((TMN * W) % CW == 0 && (TK * W) % CW == 0, "chunks straddle columns");
     static_assert((CPC_MN & (CPC_MN - 1)) == 0 && (CPC_K & (CPC_K - 1)) == 0 && CPC_MN <= NT && CPC_K <= NT,
                   "chunk grid must be a power of two no wider than the workgroup");
 
-    struct Chunk { uint4 v[NV]; };
-    Chunk raw[PER];  // one tile's loads, held until converted
+    uint4 raw[PER];  // one tile's loads, held until converted
 
     const char *base;
     int64_t ld, MN, K, mn0;
@@ -183,19 +182,16 @@ struct Stage {
         const int64_t mlim64 = MN - mn0;
         const int mlim = mlim64 > (1 << 30) ? (1 << 30) : (int)mlim64;
         const uint32_t col_bytes = (uint32_t)(ld * W * ESZ);
-        const int epos = (pos * 4) / W;  // first element of the chunk along the contiguous dim
+        const int epos = (pos * CW) / W;  // first element of the chunk along the contiguous dim
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;
             const int e_mn = MNC ? epos : col;
             const int e_k = MNC ? col : epos;
             const bool ok = (e_mn < mlim) && (e_k < klim);
-            const uint32_t off = ok ? (uint32_t)col * col_bytes + (uint32_t)(pos * 4 * ESZ) : 0x80000000u;
-#pragma unroll
-            for (int h = 0; h < NV; ++h) {
-                const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u * h), 0, 0);
-                raw[c].v[h] = make_uint4(x[0], x[1], x[2], x[3]);
-            }
+            const uint32_t off = ok ? (uint32_t)col * col_bytes + (uint32_t)(pos * 16) : 0x80000000u;
+            const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+            raw[c] = make_uint4(x[0], x[1], x[2], x[3]);
         }
     }
 
@@ -207,18 +203,15 @@ struct Stage {
         const int64_t contig_len = rows_st * W, col_stride = ld * W;
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
-            const int64_t col = c0 + col0 + c * col_step, comp0 = r0 * W + pos * 4;
+            const int64_t col = c0 + col0 + c * col_step, comp0 = r0 * W + pos * CW;
             const bool colok = col < cols_st;
             const int64_t idx = col * col_stride + comp0;
             if constexpr (SDBL) {
                 const uint2 *p = (const uint2 *)base + idx;
-                uint2 e0 = make_uint2(0u, 0u), e1 = e0, e2 = e0, e3 = e0;
+                uint2 e0 = make_uint2(0u, 0u), e1 = e0;
                 if (colok && comp0 + 0 < contig_len) e0 = p[0];
                 if (colok && comp0 + 1 < contig_len) e1 = p[1];
-                if (colok && comp0 + 2 < contig_len) e2 = p[2];
-                if (colok && comp0 + 3 < contig_len) e3 = p[3];
-                raw[c].v[0] = make_uint4(e0.x, e0.y, e1.x, e1.y);
-                raw[c].v[NV - 1] = make_uint4(e2.x, e2.y, e3.x, e3.y);
+                raw[c] = make_uint4(e0.x, e0.y, e1.x, e1.y);
             } else {
                 const uint32_t *p = (const uint32_t *)base + idx;
                 uint32_t e0 = 0u, e1 = 0u, e2 = 0u, e3 = 0u;
@@ -226,7 +219,7 @@ struct Stage {
                 if (colok && comp0 + 1 < contig_len) e1 = p[1];
                 if (colok && comp0 + 2 < contig_len) e2 = p[2];
                 if (colok && comp0 + 3 < contig_len) e3 = p[3];
-                raw[c].v[0] = make_uint4(e0, e1, e2, e3);
+                raw[c] = make_uint4(e0, e1, e2, e3);
             }
         }
     }
@@ -238,14 +231,12 @@ struct Stage {
     }
 
     // Component q of a chunk converted to the computation type.
-    __device__ __forceinline__ static T component(const Chunk &x, int q) {
+    __device__ __forceinline__ static T component(const uint4 &h, int q) {
         if constexpr (SDBL) {
-            const uint4 h = x.v[q >> 1];
-            const uint32_t w0 = (q & 1) ? h.z : h.x;
-            const uint32_t w1 = (q & 1) ? h.w : h.y;
+            const uint32_t w0 = q ? h.z : h.x;
+            const uint32_t w1 = q ? h.w : h.y;
             return (T)__builtin_bit_cast(double, ((uint64_t)w1 << 32) | w0);
         } else {
-            const uint4 h = x.v[0];
             const uint32_t w = q == 0 ? h.x : (q == 1 ? h.y : (q == 2 ? h.z : h.w));
             return (T)__builtin_bit_cast(float, w);
         }
@@ -283,9 +274,9 @@ struct Stage {
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < CW; ++q) {
                 const T v = component(raw[c], q);
-                const int e = pos * (4 / W) + q / W;
+                const int e = pos * (CW / W) + q / W;
                 const int part = q % W;
                 if constexpr (FAST) {
                     if constexpr (MNC) emit(lds, e, col, part, v, conj);
@@ -444,7 +435,7 @@ struct Frag {
 #define MD_OCC 2
 #endif
 #ifndef MD_SCHED
-#define MD_SCHED 1
+#define MD_SCHED 0
 #endif
 
 template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC>
