@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-native", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a plain copy kernel of known size (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -76,7 +78,7 @@ def make_operands(n, seed=1901):
     return ops
 
 
-def native_times(n, reps=10):
+def native_times(n, reps=20):
     """p50 seconds of torch.matmul per dtype (the native same-type GEMM)."""
     import torch
     res = {}
@@ -111,28 +113,67 @@ def native_times(n, reps=10):
     return res
 
 
+ELEM_BYTES = {"s": 4, "d": 8, "c": 8, "z": 16}
+
+
+def algorithmic_bytes(cabx, n):
+    """Bytes one product must move at least: A and B read once, C read once
+    (beta != 0) and written once."""
+    tc, ta, tb = cabx[0], cabx[1], cabx[2]
+    return n * n * (ELEM_BYTES[ta] + ELEM_BYTES[tb] + 2 * ELEM_BYTES[tc])
+
+
 def native_for(case, x):
     if case == "3":
         return "cgemm" if x == "s" else "zgemm"
     return "sgemm" if x == "s" else "dgemm"
 
 
-def traffic_record(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if
-    it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def kernel_source_sha():
+    """Hash of the sources that define the product kernels."""
+    h = hashlib.sha256()
+    for f in ("md_tile.h", "mdgemm_kernels.hip", "md_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1901_06015_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def kernel_symbol(plan, transa="N", transb="N"):
+    """The demangled symbol rocprofv3 reports for the kernel a plan launches."""
+    name = plan["kernel"]
+    t = "double" if "_f64_" in name else "float"
+    fast = "_fast_" in name
+    ad, bd = name[-2] == "d", name[-1] == "d"
+    amnc = (transa == "N") if fast else True
+    bmnc = (transb != "N") if fast else True
+    b = lambda v: "true" if v else "false"
+    return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s>(md::GemmArgs)" % (
+        t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc))
+
+
+def traffic_record(symbol):
+    """HBM bytes per launch of `symbol` (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy kernel's counters) from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    try:
-        rec = json.load(open(path))
-    except ValueError:
-        return None
-    src = os.path.join(ROOT, "paper_1901_06015_amd", "csrc", "mdgemm_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    ent = rec.get(kernel)
-    if not ent or ent.get("kernel_src_sha256") != sha:
-        return None
-    return ent.get("hbm_bytes_per_launch")
+    sha = kernel_source_sha()
+    for line in open(path):
+        parts = line.rstrip("\n").split("\t")
+        if len(parts) == 5 and parts[0] == symbol and parts[1] == sha:
+            return {"fetch_bytes": float(parts[2]), "write_bytes": float(parts[3]),
+                    "bytes": float(parts[4]), "source": "profiles/hbm_traffic.txt"}
+    return None
+
+
+def copy_calibration(nbytes=256 << 20, reps=3):
+    """A plain elementwise copy of known size (read n bytes, write n bytes)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(budget_s):
@@ -231,6 +272,8 @@ def main():
     value = step_flops / (ms / 1e3) / 1e9
 
     native = native_times(n) if not args.no_native else {}
+    if args.calibrate_copy:
+        copy_calibration()
     per = {}
     by_kernel = {}
     for c in todo:
@@ -241,14 +284,15 @@ def main():
         per[c] = {"case": plans[c]["case"], "gflops": round(gf, 1),
                   "vs_native": round(gf / nat["gflops"], 3) if nat else None,
                   "p50_ms": round(p50 * 1e3, 4), "p99_ms": round(float(np.percentile(ts, 99)) * 1e3, 4)}
-        k = plans[c]["kernel"]
-        bk = by_kernel.setdefault(k, {"flops": 0.0, "time": 0.0, "launches": 0})
+        k = kernel_symbol(plans[c])
+        bk = by_kernel.setdefault(k, {"flops": 0.0, "time": 0.0, "launches": 0, "bytes": 0.0})
         bk["flops"] += flops[c] * len(ts)
+        bk["bytes"] += algorithmic_bytes(c, n) * len(ts)
         bk["time"] += float(ts.sum())
         bk["launches"] += len(ts)
     dom = max(by_kernel, key=lambda k: by_kernel[k]["time"])
     dk = by_kernel[dom]
-    prec = "f64" if "_f64_" in dom else "f32"
+    prec = "f64" if "<double" in dom else "f32"
     achieved = dk["flops"] / dk["time"] / 1e12
     ratios = [v["vs_native"] for v in per.values() if v["vs_native"] is not None]
     out = {
@@ -278,6 +322,8 @@ def main():
                      "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_TFLOPS[prec], 4),
                      "traffic": traffic_record(dom),
+                     "algorithmic_bytes_per_launch": round(dk["bytes"] / dk["launches"]),
+                     "kernel_src": kernel_source_sha(),
                      "launches": dk["launches"],
                      "avg_launch_ms": round(dk["time"] / dk["launches"] * 1e3, 4)},
         "per_kernel": {k: {"tflops": round(v["flops"] / v["time"] / 1e12, 2),
