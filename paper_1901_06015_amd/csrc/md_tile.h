@@ -242,34 +242,43 @@ struct Stage {
         }
     }
 
-    // Place part `part` (0 Re, 1 Im) of stored element (mm, kk) of the tile.
-    __device__ __forceinline__ static void emit(T *lds, int mm, int kk, int part, T v, bool conj) {
+    // Place part `part` (0 Re, 1 Im) of stored element (mm, kk) of the tile at
+    // its position (k', m') in the real product through `out.put(k', m', v)`.
+    template <class Out>
+    __device__ __forceinline__ static void emit(Out &out, int mm, int kk, int part, T v, bool conj) {
         if constexpr (MODE == M_PLAIN) {
-            lds[L::at(kk, mm)] = v;
+            out.put(kk, mm, v);
         } else if constexpr (MODE == M_REONLY) {
-            if (part == 0) lds[L::at(kk, mm)] = v;
+            if (part == 0) out.put(kk, mm, v);
         } else {
             const T vi = conj ? -v : v;
             if constexpr (MODE == M_KINT) {
-                if (part == 0) lds[L::at(2 * kk, mm)] = v;
-                else lds[L::at(2 * kk + 1, mm)] = KNEG ? -vi : vi;
+                if (part == 0) out.put(2 * kk, mm, v);
+                else out.put(2 * kk + 1, mm, KNEG ? -vi : vi);
             } else if constexpr (MODE == M_MNINT) {
-                if (part == 0) lds[L::at(kk, split_pos(mm, 0))] = v;
-                else lds[L::at(kk, split_pos(mm, 1))] = vi;
+                if (part == 0) out.put(kk, split_pos(mm, 0), v);
+                else out.put(kk, split_pos(mm, 1), vi);
             } else {  // M_ONEE: [re -im; im re] per complex element (Eq. 1mc)
                 if (part == 0) {
-                    lds[L::at(2 * kk, split_pos(mm, 0))] = v;
-                    lds[L::at(2 * kk + 1, split_pos(mm, 1))] = v;
+                    out.put(2 * kk, split_pos(mm, 0), v);
+                    out.put(2 * kk + 1, split_pos(mm, 1), v);
                 } else {
-                    lds[L::at(2 * kk, split_pos(mm, 1))] = vi;
-                    lds[L::at(2 * kk + 1, split_pos(mm, 0))] = -vi;
+                    out.put(2 * kk, split_pos(mm, 1), vi);
+                    out.put(2 * kk + 1, split_pos(mm, 0), -vi);
                 }
             }
         }
     }
 
-    // Convert the staged registers and write them to one LDS buffer.
-    __device__ __forceinline__ void store(T *lds) const {
+    // Writes one element of the real product's tile into an LDS buffer of T.
+    struct PlainOut {
+        T *lds;
+        __device__ __forceinline__ void put(int kk, int mm, T v) const { lds[L::at(kk, mm)] = v; }
+    };
+
+    // Convert the staged registers and hand every element to `out`.
+    template <class Out>
+    __device__ __forceinline__ void store_to(Out out) const {
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;
@@ -279,16 +288,18 @@ struct Stage {
                 const int e = pos * (CW / W) + q / W;
                 const int part = q % W;
                 if constexpr (FAST) {
-                    if constexpr (MNC) emit(lds, e, col, part, v, conj);
-                    else emit(lds, col, e, part, v, conj);
+                    if constexpr (MNC) emit(out, e, col, part, v, conj);
+                    else emit(out, col, e, part, v, conj);
                 } else {
                     const int mm = mn_contig ? e : col;
                     const int kk = mn_contig ? col : e;
-                    emit(lds, mm, kk, part, v, conj);
+                    emit(out, mm, kk, part, v, conj);
                 }
             }
         }
     }
+
+    __device__ __forceinline__ void store(T *lds) const { store_to(PlainOut{lds}); }
 };
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,176 @@
+// md_tile_bf16.h -- the BF16x3 form of the product kernel (computation
+// precision MD_COMP_S_BF16X3).
+//
+// Single-precision semantics on the bfloat16 matrix cores: staging converts
+// each element to FP32 exactly as the single-precision path does, then splits
+// it into hi = bf16(a) and lo = bf16(a - hi) (both round-to-nearest-even;
+// a - hi is exact in FP32) and writes hi and lo to two LDS planes.  Each
+// product of the real product is formed from three bf16 products,
+//     a*b ~ hi_a*hi_b + hi_a*lo_b + lo_a*hi_b,
+// accumulated in FP32 by v_mfma_f32_16x16x32_bf16 (the dropped lo_a*lo_b and
+// the split residuals are below 2^-16 |a||b| per term).  The lowering of the
+// domain cases, the staging loads and the epilogue are those of md_tile.h with
+// T = float.  This precision form is an addition of this library, not of the
+// paper.
+#pragma once
+#include "md_tile.h"
+
+namespace md {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// One LDS plane of bf16: [k][mn] (row stride BMN+4) for an operand contiguous
+// along m/n, [mn][k] (row stride 40) for one contiguous along k.  The paddings
+// put the 4 lane groups of a fragment read on distinct banks.
+template <bool MNC, int BMN>
+struct LayBF {
+    static constexpr int BK = 32;
+    static constexpr int LD = MNC ? BMN + 4 : BK + 8;
+    static constexpr int SIZE = (MNC ? BK : BMN) * LD;
+    __device__ __forceinline__ static int at(int kk, int mm) { return MNC ? kk * LD + mm : mm * LD + kk; }
+};
+
+// Staging output that writes the hi and lo halves of each FP32 value.
+template <bool MNC, int BMN>
+struct SplitOut {
+    typedef LayBF<MNC, BMN> L;
+    __bf16 *hi, *lo;
+    __device__ __forceinline__ void put(int kk, int mm, float v) const {
+        const __bf16 h = (__bf16)v;
+        const __bf16 l = (__bf16)(v - (float)h);
+        hi[L::at(kk, mm)] = h;
+        lo[L::at(kk, mm)] = l;
+    }
+};
+
+// Fragment of one 16x16x32 MFMA operand for block i: lane group g = lane >> 4
+// holds k = 8g .. 8g+7 of row (or column) w0 + 16 i + (lane & 15).
+template <bool MNC, int BMN>
+__device__ __forceinline__ bf16x8 read_bf16_frag(const __bf16 *plane, int lane, int w0, int i) {
+    typedef LayBF<MNC, BMN> L;
+    const int g = lane >> 4, mm = w0 + 16 * i + (lane & 15);
+    if constexpr (MNC) {
+        bf16x8 x;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = plane[L::at(8 * g + j, mm)];
+        return x;
+    } else {
+        return *(const bf16x8 *)&plane[L::at(8 * g, mm)];
+    }
+}
+
+__device__ __forceinline__ v4f mfma_bf16(bf16x8 x, bf16x8 y, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+}
+
+template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC>
+__global__ __launch_bounds__(NT, 2) void md_bf16x3_kernel(GemmArgs g) {
+    typedef TileCfg<float> C;
+    static_assert(C::BK == 32, "one 16x16x32 step per LDS tile");
+    typedef Stage<float, CS, true, FAST, AD, AMNC> SA;
+    typedef Stage<float, CS, false, FAST, BD, BMNC> SB;
+    typedef LayBF<AMNC, C::BM> LA;
+    typedef LayBF<BMNC, C::BN> LB;
+    static_assert(SA::TK == SB::TK, "A and B disagree on the k lowering");
+    constexpr bool MDBL = SA::MN2, NDBL = SB::MN2;
+    constexpr bool CCPLX = (CS == MD_CASE_1C || CS == MD_CASE_2AC || CS == MD_CASE_2BC || CS == MD_CASE_3);
+
+    // [buffer][plane hi/lo][...]
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][2][LA::SIZE];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][LB::SIZE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
+    int tm, tn;
+    map_tile(blockIdx.x, gridDim.x, g.tiles_m, g.tiles_n, &tm, &tn);
+    const int64_t mn0a = (int64_t)tm * SA::TMN, mn0b = (int64_t)tn * SB::TMN;
+    const int nk = (int)((g.k + SA::TK - 1) / SA::TK);
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+
+    SA la(g, tid, mn0a);
+    SB lb(g, tid, mn0b);
+    auto stage_out = [&](int buf) {
+        la.store_to(SplitOut<AMNC, C::BM>{sA[buf][0], sA[buf][1]});
+        lb.store_to(SplitOut<BMNC, C::BN>{sB[buf][0], sB[buf][1]});
+    };
+    // One LDS tile = one 32-deep step: 3 bf16 MFMAs per 16x16 block.
+    auto tile = [&](int cur, bool store_next) {
+        bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ah[i] = read_bf16_frag<AMNC, C::BM>(sA[cur][0], lane, wm0, i);
+            al[i] = read_bf16_frag<AMNC, C::BM>(sA[cur][1], lane, wm0, i);
+            bh[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][0], lane, wn0, i);
+            bl[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][1], lane, wn0, i);
+        }
+        if (store_next) stage_out(cur ^ 1);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                acc[a][b] = mfma_bf16(bl[b], ah[a], acc[a][b]);
+                acc[a][b] = mfma_bf16(bh[b], al[a], acc[a][b]);
+                acc[a][b] = mfma_bf16(bh[b], ah[a], acc[a][b]);
+            }
+    };
+
+    la.load(0);
+    lb.load(0);
+    stage_out(0);
+    __syncthreads();
+    if (nk > 1) {
+        la.load(1);
+        lb.load(1);
+    }
+    int t = 0;
+    for (; t + 1 < nk; ++t) {
+        tile(t & 1, true);
+        __syncthreads();
+        if (t + 2 < nk) {
+            la.load(t + 2);
+            lb.load(t + 2);
+        }
+    }
+    tile(t & 1, false);
+
+    const int ml = lane & 15;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int nl = acc_row<float>(lane, v);
+            if constexpr (MDBL) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
+                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                    update_cplx<float>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
+                }
+            } else if constexpr (NDBL) {
+                if ((b & 1) == 0) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
+                        const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
+                        update_cplx<float>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
+                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                    if constexpr (CCPLX) update_cplx<float>(g, i, j, acc[a][b][v], 0.0f);
+                    else update_real<float>(g, i, j, acc[a][b][v]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace md

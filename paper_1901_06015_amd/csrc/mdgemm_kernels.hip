@@ -1,11 +1,12 @@
 // mdgemm_kernels.hip -- instantiations of the product kernel (md_tile.h).
 //
 // Compiled once per (computation precision, domain case) with
-// -DMD_KT=<0 single | 1 double> and -DMD_KCASE=<md_case> so that the 128
-// variants (2 computation precisions x 8 cases x 4 storage precisions of A and
+// -DMD_KT=<0 single | 1 double | 2 BF16x3> and -DMD_KCASE=<md_case> so that the 128
+// variants (3 computation precisions x 8 cases x 4 storage precisions of A and
 // B x 5 load paths: the fast path for each of the 4 operand orientations and
 // the generic path) build in parallel.
 #include "md_tile.h"
+#include "md_tile_bf16.h"
 
 #ifndef MD_KT
 #error "MD_KT must be defined"
@@ -16,20 +17,30 @@
 
 namespace md {
 
-#if MD_KT == 0
-typedef float KT;
-#else
+// MD_KT: 0 = single (FP32 MFMA), 1 = double (FP64 MFMA), 2 = BF16x3.
+#if MD_KT == 1
 typedef double KT;
+#else
+typedef float KT;
 #endif
+
+template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC>
+static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
+#if MD_KT == 2
+    hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+#else
+    hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+#endif
+}
 
 template <int CS, bool FAST, bool AMNC, bool BMNC>
 static void launch_v(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     if (a.a_dbl) {
-        if (a.b_dbl) hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, true, true, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
-        else hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, true, false, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+        if (a.b_dbl) launch_k<CS, FAST, true, true, AMNC, BMNC>(a, s, nwg);
+        else launch_k<CS, FAST, true, false, AMNC, BMNC>(a, s, nwg);
     } else {
-        if (a.b_dbl) hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, false, true, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
-        else hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, false, false, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+        if (a.b_dbl) launch_k<CS, FAST, false, true, AMNC, BMNC>(a, s, nwg);
+        else launch_k<CS, FAST, false, false, AMNC, BMNC>(a, s, nwg);
     }
 }
 

@@ -18,13 +18,17 @@ namespace md {
     void launch_part_##t##_7(const GemmArgs &, hipStream_t, unsigned);
 MD_DECL_PARTS(0)
 MD_DECL_PARTS(1)
+MD_DECL_PARTS(2)
 
 typedef void (*part_fn)(const GemmArgs &, hipStream_t, unsigned);
-static const part_fn kParts[2][8] = {
+// [PREC_S, PREC_D, PREC_BF16X3][case]
+static const part_fn kParts[3][8] = {
     {launch_part_0_0, launch_part_0_1, launch_part_0_2, launch_part_0_3,
      launch_part_0_4, launch_part_0_5, launch_part_0_6, launch_part_0_7},
     {launch_part_1_0, launch_part_1_1, launch_part_1_2, launch_part_1_3,
-     launch_part_1_4, launch_part_1_5, launch_part_1_6, launch_part_1_7}};
+     launch_part_1_4, launch_part_1_5, launch_part_1_6, launch_part_1_7},
+    {launch_part_2_0, launch_part_2_1, launch_part_2_2, launch_part_2_3,
+     launch_part_2_4, launch_part_2_5, launch_part_2_6, launch_part_2_7}};
 
 // C := beta*C (alpha == 0 or k == 0).  beta == 0 writes zeros without reading C.
 __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
@@ -66,8 +70,8 @@ int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg) 
     const int64_t n = (int64_t)a.tiles_m * a.tiles_n;
     if (wg) *wg = n;
     if (n <= 0) return 0;
-    if ((prec != PREC_D && prec != PREC_S) || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
-    kParts[prec == PREC_D ? 1 : 0][cs](a, (hipStream_t)stream, (unsigned)n);
+    if (prec < PREC_S || prec > PREC_BF16X3 || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
+    kParts[prec][cs](a, (hipStream_t)stream, (unsigned)n);
     return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
 }
 
@@ -89,7 +93,7 @@ void tile_shape(int prec, int cs, int *bm, int *bn, int *bk) {
 
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len) {
     static const char *cases[8] = {"0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3"};
-    snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c", prec == PREC_D ? "f64" : "f32",
+    snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c", prec == PREC_D ? "f64" : (prec == PREC_S ? "f32" : "bf16x3"),
              (cs >= 0 && cs < 8) ? cases[cs] : "?", (a.a_vec && a.b_vec) ? "fast" : "generic",
              a.a_dbl ? 'd' : 's', a.b_dbl ? 'd' : 's');
 }

@@ -173,3 +173,37 @@ def test_stream_argument():
     assert st == 0
     ref, g = gu.reference("z", "z", "d", 64, 64, 64, ops)
     gu.check("z", "d", 64, Cout, 64, 64, ref, g)
+
+
+# ---------------------------------------------------------------------------
+# BF16x3: single-precision semantics from three bf16 products per real product
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tc", TAGS)
+def test_bf16x3_exact_inputs_bitwise(tc):
+    """Integers in [-4, 4] are exact in bf16 (lo = 0) and every partial sum is
+    exact in FP32, so the BF16x3 path must equal the oracle bit for bit."""
+    for ta, tb in itertools.product(TAGS, TAGS):
+        say("bf16x3 exact %s%s%s" % (tc, ta, tb))
+        m, n, k = 70, 66, 45
+        st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp="bf16x3", dist="int", seed=13)
+        assert st == 0, st
+        ref, _ = gu.reference(tc, ta, tb, m, n, k, ops)
+        got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+        assert np.array_equal(got, ref), "bf16x3 exact %s%s%s: %d mismatches" % (
+            tc, ta, tb, int((got != ref).sum()))
+
+
+@pytest.mark.parametrize("tc", TAGS)
+def test_bf16x3_within_single_precision_bound(tc):
+    """Random inputs at k >= 96, where the split's per-term error (below
+    3*2^-18 |a||b|) plus FP32 accumulation stays inside 4 k u_s (|A||B|)."""
+    for ta, tb in itertools.product(TAGS, TAGS):
+        one(tc, ta, tb, 150, 140, 130, "bf16x3")
+
+
+def test_bf16x3_transposes_and_loguniform():
+    for transa, transb in (("T", "N"), ("N", "T"), ("C", "C")):
+        for cab in ("sss", "css", "ccs", "ccc", "zdz"):
+            one(cab[0], cab[1], cab[2], 131, 97, 160, "bf16x3", transa, transb)
+    for cab in ("sss", "css", "ccs", "ccc"):
+        one(cab[0], cab[1], cab[2], 128, 128, 256, "bf16x3", dist="loguniform", beta=0.0)
