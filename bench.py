@@ -49,6 +49,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain copy kernel of known size (HBM counter calibration)")
+    p.add_argument("--workload", default="sweep", choices=["sweep", "precision", "grouped", "serving"],
+                   help="sweep: the 128-combination plain method at 4096 (default); precision: "
+                        "FP32 vs BF16x3 at 8192; grouped: 512 mixed GEMMs in one launch; serving: "
+                        "Poisson request stream")
     return p.parse_args()
 
 
@@ -209,12 +213,103 @@ def cpu_baseline(budget_s):
                       % (", ".join("%s:%d cols" % kv for kv in cols_done.items()), total_t)}
 
 
+def precision_workload(args):
+    """FP32 MFMA vs BF16x3 at m=n=k=size (8192 by default) for ssss, csss,
+    ccss, cccs (the cab(x) reading of the combinations) and scss, sccs (the
+    other reading), each with U[-1,1] and log-uniform 10^U(-3,3) entries,
+    alpha = 1, beta = 0.  Errors: against the CPU oracle on 512 sampled
+    entries (the bound ratio and |dC|/(|A||B|)), and normwise against a full
+    FP64 reference product (torch.matmul in complex128 on the promoted
+    operands, checked against the same oracle samples)."""
+    import torch
+    import oracle
+    from paper_1901_06015_amd import _lib, inputs
+    n = args.size if args.size != 4096 else 8192
+    o = oracle.get()
+    sp = torch.cuda.current_stream().cuda_stream
+    rng = np.random.Generator(np.random.PCG64(77))
+    rows = np.concatenate([[0, n - 1, 0, n - 1, 127, 128], rng.integers(0, n, 506)]).astype(np.int64)
+    cols = np.concatenate([[0, 0, n - 1, n - 1, 128, 127], rng.integers(0, n, 506)]).astype(np.int64)
+    out = {}
+    total = {"s": [0.0, 0.0], "bf16x3": [0.0, 0.0]}
+    for cab in ("sss", "css", "ccs", "ccc", "scs", "scc"):
+        for dist in ("uniform", "loguniform"):
+            tc, ta, tb = cab
+            key = cab + "s/" + dist
+            print("# precision %s" % key, file=sys.stderr, flush=True)
+            A = inputs.matrix(n, n, ta, 301, dist=dist)
+            B = inputs.matrix(n, n, tb, 302, dist=dist)
+            C0 = inputs.matrix(n, n, tc, 303, dist=dist)
+            dA = torch.from_numpy(A).cuda()
+            dB = torch.from_numpy(B).cuda()
+            st, ref_s, g_s = o.gemm_at("N", "N", n, n, n, 1.0, A, ta, n, B, tb, n, 0.0, C0, tc, n, rows, cols)
+            assert st == 0
+            # FP64 reference product of the promoted operands
+            Ar = dA.to(torch.complex128)
+            Br = dB.to(torch.complex128)
+            Cref = torch.matmul(Ar, Br)
+            del Ar, Br
+            if tc in "sd":
+                Cref = Cref.real.to(torch.complex128)
+            lib_ref = Cref[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
+            ref_check = float(np.max(np.abs(lib_ref - ref_s) / np.maximum(g_s, 1e-300)))
+            res = {"fp64_reference_vs_oracle_max_rel": ref_check}
+            for comp in ("s", "bf16x3"):
+                dC = torch.from_numpy(C0).cuda()
+                ts = []
+                for r in range(1 + args.steps):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    stx = _lib.mdgemm("N", "N", n, n, n, 1.0, dA.data_ptr(), ta, n, dB.data_ptr(), tb, n,
+                                      0.0, dC.data_ptr(), tc, n, comp, sp)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    assert stx == 0
+                    if r > 0:
+                        ts.append(e0.elapsed_time(e1) / 1e3)
+                p50 = float(np.median(ts))
+                st, pl = _lib.mdgemm_plan("N", "N", n, n, n, 1.0, 1, ta, n, 1, tb, n, 0.0, 1, tc, n, comp)
+                gf = pl["flops"] / p50 / 1e9
+                got = dC[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.complex128)
+                err = np.abs(got - ref_s)
+                bound = 4 * n * 2.0 ** -24 * g_s + 4 * (2.0 ** -24 if tc in "sc" else 2.0 ** -53) * np.abs(ref_s)
+                full = dC.to(torch.complex128)
+                nf = float(torch.linalg.norm(full - Cref) / torch.linalg.norm(Cref))
+                del full, dC
+                res[comp] = {"p50_ms": round(p50 * 1e3, 3), "gflops": round(gf, 1),
+                             "max_err_over_bound": float(np.max(err / bound)),
+                             "median_err_over_AB": float(np.median(err / g_s)),
+                             "max_err_over_AB": float(np.max(err / g_s)),
+                             "normwise_rel_err": nf}
+                total[comp][0] += pl["flops"]
+                total[comp][1] += p50
+            res["bf16x3_speedup"] = round(res["s"]["p50_ms"] / res["bf16x3"]["p50_ms"], 3)
+            out[key] = res
+            del dA, dB, Cref
+            torch.cuda.empty_cache()
+    agg = {c: v[0] / v[1] / 1e9 for c, v in total.items()}
+    line = {"metric": "GFLOP/s FP32-MFMA vs BF16x3 at m=n=k=%d, error vs FP64 oracle" % n,
+            "value": round(agg["bf16x3"], 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "higher_is_better": True, "dtype": "bf16x3 (f32 semantics)", "data": "synthetic",
+            "config": {"workload": "precision form: m=n=k=%d, combos ssss csss ccss cccs scss sccs, "
+                                   "U[-1,1] and 10^U(-3,3), alpha=1, beta=0" % n},
+            "fp32_gflops": round(agg["s"], 1),
+            "speedup_bf16x3_over_fp32": round(agg["bf16x3"] / agg["s"], 3),
+            "roofline": {"bf16x3_vs_fp32_peak": round(agg["bf16x3"] / 157.3e3, 4),
+                         "bf16_mfma_utilisation": round(3 * agg["bf16x3"] / 2.5e6, 4)},
+            "per_combo": out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "precision":
+        return precision_workload(args)
     import torch
     from paper_1901_06015_amd import _lib, api
     _lib.lib()
