@@ -141,9 +141,11 @@ int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k,
  * computation precision.  Every descriptor is validated first; if any is
  * invalid the call returns -(1000*index + i) for the first bad argument i of
  * descriptor `index` (or MD_ERR_ALPHA_IMAG) and enqueues nothing.  The C
- * operands must be pairwise disjoint.  The library keeps an internal device
- * work table that it grows as needed; calls on one device are serialised
- * internally up to the enqueue.
+ * operands must be pairwise disjoint and must not overlap any A or B.  The
+ * work table (one entry per product and per output tile, largest work first)
+ * is uploaded into a stream-ordered device allocation that is released,
+ * again in stream order, after the kernel; nothing else is allocated.  The
+ * tile shape of each product comes from the tile-shape table below.
  */
 typedef struct {
     char transa, transb;
@@ -158,11 +160,27 @@ typedef struct {
 
 int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream);
 
-/* Tile table used for the grouped kernel's work decomposition and the plain
- * path's tile choice: load one written by the autotuner (a small text file,
- * see the autotuner's documentation), or reset to the built-in defaults with
- * path == NULL.  Returns 0 or MD_ERR_STATE if the file is malformed. */
+/*
+ * Tile-shape table of the grouped kernel: for each computation precision
+ * (md_comp S, D or S_BF16X3), domain case (md_case) and size bucket (by the
+ * larger dimension of the real product the case lowers to: 0: <=64, 1: <=128,
+ * 2: <=256, 3: <=512, 4: <=1024, 5: larger) the workgroup tile edge, 64 or
+ * 128 (BF16x3 products always use 64).  The autotuner measures both and
+ * writes a text table, one entry per
+ * line: "comp case bucket tile" (comp s|d|bf16x3, case 0|1a|1b|1c|2ab|2ac|2bc|3),
+ * '#' comments.
+ *
+ * mdgemm_tune_load: reset to the built-in defaults, then apply the file at
+ *   `path` (NULL: defaults only).  Returns 0, or MD_ERR_STATE (table
+ *   unchanged) if the file is missing or malformed.
+ * mdgemm_tune_set: set one entry; returns 0 or MD_ERR_STATE for an invalid
+ *   entry.
+ * mdgemm_tune_get: the current tile edge of one entry, or -1 if invalid.
+ * The table is process-wide and guarded by a lock.
+ */
 int mdgemm_tune_load(const char *path);
+int mdgemm_tune_set(int comp, int domain_case, int bucket, int tile);
+int mdgemm_tune_get(int comp, int domain_case, int bucket);
 
 /* Human-readable text for a status code. */
 const char *mdgemm_strerror(int status);

@@ -67,6 +67,10 @@ def lib():
         L.mdgemm_grouped.restype = ci
         L.mdgemm_tune_load.argtypes = [ctypes.c_char_p]
         L.mdgemm_tune_load.restype = ci
+        L.mdgemm_tune_set.argtypes = [ci, ci, ci, ci]
+        L.mdgemm_tune_set.restype = ci
+        L.mdgemm_tune_get.argtypes = [ci, ci, ci]
+        L.mdgemm_tune_get.restype = ci
         L.mdgemm_strerror.argtypes = [ci]
         L.mdgemm_strerror.restype = ctypes.c_char_p
         L.mdgemm_version.argtypes = []
@@ -125,3 +129,17 @@ def mdgemm_grouped(descs, stream=None):
 
 def strerror(status):
     return lib().mdgemm_strerror(status).decode()
+
+
+def tune_load(path):
+    return lib().mdgemm_tune_load(None if path is None else path.encode())
+
+
+def tune_set(comp, case, bucket, tile):
+    return lib().mdgemm_tune_set(comp_tag(comp), CASE_NAMES.index(case) if isinstance(case, str) else case,
+                                 bucket, tile)
+
+
+def tune_get(comp, case, bucket):
+    return lib().mdgemm_tune_get(comp_tag(comp), CASE_NAMES.index(case) if isinstance(case, str) else case,
+                                 bucket)

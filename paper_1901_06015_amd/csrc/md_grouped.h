@@ -1,0 +1,443 @@
+// md_grouped.h -- the persistent kernel behind mdgemm_grouped: many products
+// of uneven shapes and mixed storage types / computation precisions in ONE
+// launch.
+//
+// The host builds a work table (one GDesc per product, one GTile per output
+// tile, largest work first) and the kernel's workgroups pop tile indices from
+// an atomic counter until the table is exhausted.  Because one launch mixes
+// every variant, the tile routine decodes the domain case, the storage
+// precisions and the operand orientation at run time, element by element
+// (`fetch_elem`), instead of using the specialised staging of md_tile.h; the
+// lowering it realises is the same (Figure "mixeddom" cases onto one real
+// product, Re/Im split in blocks of 16, 1e/1r arrangement for case 3), and the
+// epilogue is md_tile.h's.
+#pragma once
+#include "md_tile.h"
+#include "md_tile_bf16.h"
+
+namespace md {
+
+// Tile shapes of the grouped kernel (real-product workgroup tile).
+enum { GCFG_64 = 0, GCFG_128 = 1, GCFG_COUNT = 2 };
+
+struct GDesc {
+    GemmArgs g;
+    int prec;   // PREC_S / PREC_D / PREC_BF16X3
+    int cs;     // md_case
+    int cfg;    // GCFG_*
+    int kind;   // 0: product; 1: C := beta*C only (alpha == 0 or k == 0)
+    int tiles_m, tiles_n;
+};
+
+struct GTile {
+    int desc, tm, tn, pad;
+};
+
+// LDS bytes of each tile routine: two k-tiles ([k][mn], padded) of T, or
+// four bf16 planes for BF16x3; the kernel reserves the largest.
+template <class T, int WB>
+struct GShape {
+    static constexpr int BM = 32 * WB;
+    static constexpr int BK = (sizeof(T) == 8 ? 16 : 32) * 2 / WB;
+    static constexpr int LDW = BM + (sizeof(T) == 8 ? 8 : 4);
+    static constexpr int SMEM = 2 * BK * LDW * (int)sizeof(T);
+};
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int BF16X3_GROUPED_SMEM = 4 * 32 * (64 + 4) * 2;
+constexpr int GROUPED_SMEM = cmax(cmax(cmax(GShape<float, 2>::SMEM, GShape<float, 4>::SMEM),
+                                       cmax(GShape<double, 2>::SMEM, GShape<double, 4>::SMEM)),
+                                  BF16X3_GROUPED_SMEM);
+
+// Runtime description of one staged operand (A' or B').
+struct GOp {
+    const char *base;
+    int64_t ld, MN, K;
+    int mode;
+    bool dbl, cplx, mnc, conj, kneg;
+};
+
+__device__ __forceinline__ int mode_rt(int cs, bool is_a) {
+    if (is_a) {
+        return cs == MD_CASE_1A ? M_REONLY
+             : cs == MD_CASE_2AB ? M_KINT
+             : cs == MD_CASE_2AC ? M_MNINT
+             : cs == MD_CASE_3 ? M_ONEE : M_PLAIN;
+    }
+    return cs == MD_CASE_1B ? M_REONLY
+         : (cs == MD_CASE_2AB || cs == MD_CASE_3) ? M_KINT
+         : cs == MD_CASE_2BC ? M_MNINT : M_PLAIN;
+}
+
+__device__ __forceinline__ GOp make_gop(const GemmArgs &g, int cs, bool is_a) {
+    GOp o;
+    const int tr = is_a ? g.ta : g.tb;
+    o.base = (const char *)(is_a ? g.A : g.B);
+    o.ld = is_a ? g.lda : g.ldb;
+    o.MN = is_a ? g.m : g.n;
+    o.K = g.k;
+    o.mode = mode_rt(cs, is_a);
+    o.dbl = is_a ? g.a_dbl : g.b_dbl;
+    o.cplx = o.mode != M_PLAIN;
+    o.mnc = is_a ? (tr == 0) : (tr != 0);
+    o.conj = tr == 2;
+    o.kneg = is_a;
+    return o;
+}
+
+__device__ __forceinline__ bool gop_mn2(const GOp &o) { return o.mode == M_MNINT || o.mode == M_ONEE; }
+__device__ __forceinline__ bool gop_k2(const GOp &o) { return o.mode == M_KINT || o.mode == M_ONEE; }
+
+// Per-thread staging plan for E elements of a tile: for each element the
+// byte offset of its stored component at k-tile 0, whether it lies inside the
+// matrix along m/n, its k index inside the tile and its sign.  A k-tile t only
+// adds t*TK*kstride, so the loop carries no 64-bit index arithmetic.
+template <int E>
+struct GStager {
+    const char *base;
+    int64_t off[E];
+    int kp[E];
+    bool mn_ok[E], neg[E];
+    int64_t kstride;  // bytes between consecutive stored k
+    int64_t K;
+    bool dbl;
+    __device__ __forceinline__ void init(const GOp &o, int64_t mn0, int BMN, int tid) {
+        base = o.base;
+        dbl = o.dbl;
+        K = o.K;
+        const int W = o.cplx ? 2 : 1, esz = o.dbl ? 8 : 4;
+        kstride = (o.mnc ? o.ld : 1) * W * esz;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = tid + e * NT, kr = idx / BMN, mr = idx % BMN;
+            int i = mr, qm = 0;
+            if (gop_mn2(o)) {
+                const int blk = mr >> 4;
+                qm = blk & 1;
+                i = ((blk >> 1) << 4) | (mr & 15);
+            }
+            int p = kr, qk = 0;
+            if (gop_k2(o)) {
+                p = kr >> 1;
+                qk = kr & 1;
+            }
+            int comp = 0;
+            bool ng = false;
+            if (o.mode == M_KINT) {
+                comp = qk;
+                ng = qk && o.kneg;
+            } else if (o.mode == M_MNINT) {
+                comp = qm;
+            } else if (o.mode == M_ONEE) {
+                comp = qm ^ qk;
+                ng = (qm == 0 && qk == 1);
+            }
+            if (comp == 1 && o.conj) ng = !ng;
+            const int64_t mn = mn0 + i;
+            mn_ok[e] = mn < o.MN;
+            kp[e] = p;
+            neg[e] = ng;
+            const int64_t elem = o.mnc ? (mn + (int64_t)p * o.ld) : ((int64_t)p + mn * o.ld);
+            off[e] = (elem * W + comp) * esz;
+        }
+    }
+    // Element e of the k-tile starting at stored k index k0 (zero outside).
+    __device__ __forceinline__ double get(int e, int64_t k0) const {
+        if (!mn_ok[e] || k0 + kp[e] >= K) return 0.0;
+        const char *p = base + off[e] + k0 * kstride;
+        const double v = dbl ? *(const double *)p : (double)*(const float *)p;
+        return neg[e] ? -v : v;
+    }
+};
+
+// Epilogue shared by the grouped tile routines: acc[a][b] item v is
+// C'(m = wm0 + 16a + (lane & 15), n = wn0 + 16b + acc_row(lane, v)).
+template <class T, class ACC, int WB>
+__device__ __forceinline__ void grouped_epilogue(const GemmArgs &g, bool mdbl, bool ndbl, bool ccplx,
+                                                 int64_t i0, int64_t j0, int wm0, int wn0, int lane,
+                                                 ACC (&acc)[WB][WB]) {
+    const int ml = lane & 15;
+#pragma unroll
+    for (int b = 0; b < WB; ++b) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int nl = acc_row<T>(lane, v);
+            if (mdbl) {
+#pragma unroll
+                for (int q = 0; q < WB / 2; ++q) {
+                    const int64_t i = i0 + wm0 / 2 + q * 16 + ml;
+                    const int64_t j = j0 + wn0 + b * 16 + nl;
+                    update_cplx<T>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
+                }
+            } else if (ndbl) {
+                if ((b & 1) == 0) {
+#pragma unroll
+                    for (int a = 0; a < WB; ++a) {
+                        const int64_t i = i0 + wm0 + a * 16 + ml;
+                        const int64_t j = j0 + wn0 / 2 + (b / 2) * 16 + nl;
+                        update_cplx<T>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < WB; ++a) {
+                    const int64_t i = i0 + wm0 + a * 16 + ml;
+                    const int64_t j = j0 + wn0 + b * 16 + nl;
+                    if (ccplx) update_cplx<T>(g, i, j, acc[a][b][v], (T)0);
+                    else update_real<T>(g, i, j, acc[a][b][v]);
+                }
+            }
+        }
+    }
+}
+
+// One output tile of a product computed in T (float or double) with FP32 /
+// FP64 MFMA.  WB: 16x16 blocks per wave and dimension (2: 64x64 workgroup
+// tile; 4: 128x128).  LDS holds one k-tile of A' and B' as [k][mn]; the next
+// k-tile's elements are prefetched into registers during the MFMAs.
+template <class T, int WB>
+__device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, char *smem) {
+    typedef typename AccT<T>::type acc_t;
+    // k depth per LDS tile: the 128x128 shape halves it so that every shape
+    // stages the same number of elements per thread (8 per operand for f32,
+    // 4 for f64)
+    typedef GShape<T, WB> SH;
+    constexpr int BM = SH::BM, BN = SH::BM, BK = SH::BK, LDW = SH::LDW;
+    static_assert(SH::SMEM <= GROUPED_SMEM, "grouped LDS too small");
+    constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
+    T *la = (T *)smem;
+    T *lb = la + BK * LDW;
+    const GemmArgs &g = d.g;
+    const GOp oa = make_gop(g, d.cs, true), ob = make_gop(g, d.cs, false);
+    const bool mdbl = gop_mn2(oa), ndbl = gop_mn2(ob), kdbl = gop_k2(oa);
+    const bool ccplx = g.c_cplx;
+    const int tmn_a = mdbl ? BM / 2 : BM, tmn_b = ndbl ? BN / 2 : BN, tk = kdbl ? BK / 2 : BK;
+    const int64_t mn0a = (int64_t)tm * tmn_a, mn0b = (int64_t)tn * tmn_b;
+    const int nk = (int)((g.k + tk - 1) / tk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave & 1) * 16 * WB, wn0 = (wave >> 1) * 16 * WB;
+
+    acc_t acc[WB][WB];
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    GStager<EA> sa;
+    GStager<EB> sb;
+    sa.init(oa, mn0a, BM, tid);
+    sb.init(ob, mn0b, BN, tid);
+    T ra[EA], rb[EB];  // converted on load: float -> double is exact, double -> float rounds
+    auto load = [&](int t) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) ra[e] = (T)sa.get(e, (int64_t)t * tk);
+#pragma unroll
+        for (int e = 0; e < EB; ++e) rb[e] = (T)sb.get(e, (int64_t)t * tk);
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) {
+            const int idx = tid + e * NT;
+            la[(idx / BM) * LDW + idx % BM] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int idx = tid + e * NT;
+            lb[(idx / BN) * LDW + idx % BN] = rb[e];
+        }
+    };
+
+    load(0);
+    store();
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        if (t + 1 < nk) load(t + 1);
+#pragma unroll
+        for (int s = 0; s < BK / 4; ++s) {
+            const int kr = s * 4 + (lane >> 4);
+            T fa[WB], fb[WB];
+#pragma unroll
+            for (int i = 0; i < WB; ++i) fa[i] = la[kr * LDW + wm0 + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < WB; ++i) fb[i] = lb[kr * LDW + wn0 + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < WB; ++a)
+#pragma unroll
+                for (int b = 0; b < WB; ++b) acc[a][b] = mfma16(fb[b], fa[a], acc[a][b]);
+        }
+        __syncthreads();
+        if (t + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+    grouped_epilogue<T, acc_t, WB>(g, mdbl, ndbl, ccplx, (int64_t)tm * tmn_a, (int64_t)tn * tmn_b, wm0, wn0,
+                                   lane, acc);
+}
+
+// BF16x3 form of grouped_tile: single-precision semantics from three bf16
+// products per 16x16x32 block (see md_tile_bf16.h).
+template <int WB>
+__device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int tn, char *smem) {
+    constexpr int BM = 32 * WB, BN = 32 * WB, BK = 32;
+    constexpr int LDW = BM + 4;
+    static_assert(4 * BK * LDW * 2 <= GROUPED_SMEM, "grouped LDS too small");
+    constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
+    __bf16 *ah = (__bf16 *)smem;
+    __bf16 *al = ah + BK * LDW;
+    __bf16 *bh = al + BK * LDW;
+    __bf16 *bl = bh + BK * LDW;
+    const GemmArgs &g = d.g;
+    const GOp oa = make_gop(g, d.cs, true), ob = make_gop(g, d.cs, false);
+    const bool mdbl = gop_mn2(oa), ndbl = gop_mn2(ob), kdbl = gop_k2(oa);
+    const bool ccplx = g.c_cplx;
+    const int tmn_a = mdbl ? BM / 2 : BM, tmn_b = ndbl ? BN / 2 : BN, tk = kdbl ? BK / 2 : BK;
+    const int64_t mn0a = (int64_t)tm * tmn_a, mn0b = (int64_t)tn * tmn_b;
+    const int nk = (int)((g.k + tk - 1) / tk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave & 1) * 16 * WB, wn0 = (wave >> 1) * 16 * WB;
+
+    v4f acc[WB][WB];
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+
+    GStager<EA> sa;
+    GStager<EB> sb;
+    sa.init(oa, mn0a, BM, tid);
+    sb.init(ob, mn0b, BN, tid);
+    float ra[EA], rb[EB];
+    auto load = [&](int t) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) ra[e] = (float)sa.get(e, (int64_t)t * tk);
+#pragma unroll
+        for (int e = 0; e < EB; ++e) rb[e] = (float)sb.get(e, (int64_t)t * tk);
+    };
+    auto split = [](float v, __bf16 &h, __bf16 &l) {
+        h = (__bf16)v;
+        l = (__bf16)(v - (float)h);
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) {
+            const int idx = tid + e * NT, o = (idx / BM) * LDW + idx % BM;
+            split(ra[e], ah[o], al[o]);
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int idx = tid + e * NT, o = (idx / BN) * LDW + idx % BN;
+            split(rb[e], bh[o], bl[o]);
+        }
+    };
+    auto frag = [&](const __bf16 *plane, int w0, int i) {
+        bf16x8 x;
+        const int gq = lane >> 4, mm = w0 + 16 * i + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = plane[(8 * gq + j) * LDW + mm];
+        return x;
+    };
+
+    load(0);
+    store();
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        if (t + 1 < nk) load(t + 1);
+        bf16x8 fah[WB], fal[WB], fbh[WB], fbl[WB];
+#pragma unroll
+        for (int i = 0; i < WB; ++i) {
+            fah[i] = frag(ah, wm0, i);
+            fal[i] = frag(al, wm0, i);
+            fbh[i] = frag(bh, wn0, i);
+            fbl[i] = frag(bl, wn0, i);
+        }
+#pragma unroll
+        for (int a = 0; a < WB; ++a)
+#pragma unroll
+            for (int b = 0; b < WB; ++b) {
+                acc[a][b] = mfma_bf16(fbl[b], fah[a], acc[a][b]);
+                acc[a][b] = mfma_bf16(fbh[b], fal[a], acc[a][b]);
+                acc[a][b] = mfma_bf16(fbh[b], fah[a], acc[a][b]);
+            }
+        __syncthreads();
+        if (t + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+    grouped_epilogue<float, v4f, WB>(g, mdbl, ndbl, ccplx, (int64_t)tm * tmn_a, (int64_t)tn * tmn_b, wm0, wn0,
+                                     lane, acc);
+}
+
+// C := beta*C on a 64x64 region (products with alpha == 0 or k == 0).
+__device__ __forceinline__ void grouped_scale_tile(const GemmArgs &g, int tm, int tn) {
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+        const int64_t i = (int64_t)tm * 64 + (e & 63), j = (int64_t)tn * 64 + (e >> 6);
+        if (i >= g.m || j >= g.n) continue;
+        const int64_t off = i + j * g.ldc;
+        if (g.c_cplx) {
+            if (g.c_dbl) {
+                double *c = (double *)g.C + 2 * off;
+                if (g.beta_zero) { c[0] = 0.0; c[1] = 0.0; }
+                else {
+                    const double cr = c[0], ci = c[1];
+                    c[0] = fma(g.beta_re, cr, -(g.beta_im * ci));
+                    c[1] = fma(g.beta_re, ci, g.beta_im * cr);
+                }
+            } else {
+                float *c = (float *)g.C + 2 * off;
+                if (g.beta_zero) { c[0] = 0.0f; c[1] = 0.0f; }
+                else {
+                    const float br = (float)g.beta_re, bi = (float)g.beta_im, cr = c[0], ci = c[1];
+                    c[0] = fmaf(br, cr, -(bi * ci));
+                    c[1] = fmaf(br, ci, bi * cr);
+                }
+            }
+        } else if (g.c_dbl) {
+            double *c = (double *)g.C;
+            c[off] = g.beta_zero ? 0.0 : g.beta_re * c[off];
+        } else {
+            float *c = (float *)g.C;
+            c[off] = g.beta_zero ? 0.0f : (float)g.beta_re * c[off];
+        }
+    }
+}
+
+
+
+// The persistent kernel.  `hdr[0]` is the tile counter (zeroed by the host's
+// upload of the table); every workgroup exits once the counter passes
+// `ntiles`.
+__global__ __launch_bounds__(NT, 2) void md_grouped_kernel(const GDesc *descs, const GTile *tiles, int ntiles,
+                                                            int *hdr) {
+    __shared__ __attribute__((aligned(16))) char smem[GROUPED_SMEM];
+    __shared__ int s_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(hdr, 1);
+        __syncthreads();
+        // the tile index is uniform across the workgroup: keep it (and the
+        // descriptor loads that depend on it) in scalar registers
+        const int t = __builtin_amdgcn_readfirstlane(s_t);
+        __syncthreads();
+        if (t >= ntiles) break;
+        const GTile tl = tiles[t];
+        const GDesc &d = descs[__builtin_amdgcn_readfirstlane(tl.desc)];
+        const int tm = __builtin_amdgcn_readfirstlane(tl.tm), tn = __builtin_amdgcn_readfirstlane(tl.tn);
+        if (d.kind == 1) {
+            grouped_scale_tile(d.g, tm, tn);
+            continue;
+        }
+        const int sel = d.prec * GCFG_COUNT + d.cfg;
+        switch (sel) {
+        case PREC_S * GCFG_COUNT + GCFG_64: grouped_tile<float, 2>(d, tm, tn, smem); break;
+        case PREC_S * GCFG_COUNT + GCFG_128: grouped_tile<float, 4>(d, tm, tn, smem); break;
+        case PREC_D * GCFG_COUNT + GCFG_64: grouped_tile<double, 2>(d, tm, tn, smem); break;
+        case PREC_D * GCFG_COUNT + GCFG_128: grouped_tile<double, 4>(d, tm, tn, smem); break;
+        // BF16x3 has a single (64x64) shape in the grouped kernel
+        case PREC_BF16X3 * GCFG_COUNT + GCFG_64:
+        case PREC_BF16X3 * GCFG_COUNT + GCFG_128: grouped_tile_bf16x3<2>(d, tm, tn, smem); break;
+        default: break;
+        }
+    }
+}
+
+}  // namespace md

@@ -69,6 +69,19 @@ struct GemmArgs {
 
 enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
 
+// Everything mdgemm decides before touching the device (mdgemm_api.cpp).
+struct Decision {
+    int status = MD_OK;
+    int cs = MD_CASE_0;
+    int prec = PREC_S;
+    int quick = 0;  // 0 full product, 1 no-op, 2 C := beta*C
+    GemmArgs g{};
+};
+
+Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
+                const void *A, int dta, int64_t lda, const void *B, int dtb, int64_t ldb,
+                md_scalar beta, void *C, int dtc, int64_t ldc, int comp);
+
 // Host-side launchers (defined in mdgemm_kernels.hip).
 int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out);
 int launch_scale(const GemmArgs &a, void *stream);

@@ -25,14 +25,13 @@ bool dt_dbl(int dt) { return dt == MD_D || dt == MD_Z; }
 int dt_bytes(int dt) { return dt == MD_S ? 4 : (dt == MD_Z ? 16 : 8); }
 int64_t max1(int64_t v) { return v > 1 ? v : 1; }
 
-// Everything mdgemm decides before touching the device.
-struct Decision {
-    int status = MD_OK;
-    int cs = MD_CASE_0;
-    int prec = PREC_S;
-    int quick = 0;  // 0 full product, 1 no-op, 2 C := beta*C
-    GemmArgs g{};
-};
+}  // namespace
+
+namespace {
+
+}  // namespace
+
+namespace md {
 
 Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
                 const void *A, int dta, int64_t lda, const void *B, int dtb, int64_t ldb,
@@ -108,7 +107,7 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     return d;
 }
 
-}  // namespace
+}  // namespace md
 
 extern "C" {
 
@@ -180,10 +179,3 @@ const char *mdgemm_version(void) { return "mdgemm 0.1 gfx950"; }
 
 }  // extern "C"
 
-// Placeholders until the grouped kernel and its tile table land: the
-// symbols exist so that the ABI is complete, and they refuse the call.
-extern "C" int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
-    (void)descs; (void)stream;
-    return count == 0 ? MD_OK : MD_ERR_UNSUPPORTED;
-}
-extern "C" int mdgemm_tune_load(const char *path) { return path ? MD_ERR_UNSUPPORTED : MD_OK; }

@@ -1,0 +1,204 @@
+// mdgemm_grouped.hip -- host side of mdgemm_grouped (work table, tile order,
+// one persistent launch) and of the tile-shape table the autotuner writes.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "md_grouped.h"
+
+namespace md {
+namespace {
+
+// Tile-shape table: for (computation precision, domain case, size bucket) the
+// grouped kernel's tile shape.  Buckets are by the larger dimension of the
+// real product: <=64, <=128, <=256, <=512, <=1024, larger.
+constexpr int NBUCKET = 6;
+int g_table[3][8][NBUCKET];
+std::mutex g_table_mu;
+bool g_table_init = false;
+
+void default_table() {
+    for (int p = 0; p < 3; ++p)
+        for (int c = 0; c < 8; ++c)
+            for (int b = 0; b < NBUCKET; ++b) g_table[p][c][b] = (b <= 2 || p == PREC_BF16X3) ? GCFG_64 : GCFG_128;
+    g_table_init = true;
+}
+
+int bucket_of(int64_t dim) {
+    int b = 0;
+    for (int64_t lim = 64; b < NBUCKET - 1 && dim > lim; lim *= 2) ++b;
+    return b;
+}
+
+int choose_cfg(int prec, int cs, int64_t m_real, int64_t n_real) {
+    if (prec == PREC_BF16X3) return GCFG_64;  // the only BF16x3 shape of the grouped kernel
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    if (!g_table_init) default_table();
+    return g_table[prec][cs][bucket_of(std::max(m_real, n_real))];
+}
+
+int g_num_cu = 0;
+
+int num_cu() {
+    if (g_num_cu == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        g_num_cu = v;
+    }
+    return g_num_cu;
+}
+
+}  // namespace
+}  // namespace md
+
+using namespace md;
+
+extern "C" {
+
+int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
+    if (count < 0) return -1;
+    if (count == 0) return MD_OK;
+    if (!descs) return -2;
+    std::vector<GDesc> gd;
+    std::vector<GTile> tiles;
+    std::vector<double> work;
+    gd.reserve(count);
+    for (int64_t i = 0; i < count; ++i) {
+        const md_gemm_desc &x = descs[i];
+        Decision d = decide(x.transa, x.transb, x.m, x.n, x.k, x.alpha, x.A, x.dta, x.lda, x.B, x.dtb, x.ldb,
+                            x.beta, x.C, x.dtc, x.ldc, x.comp);
+        if (d.status < 0) return -(int)(1000 * i + (-d.status));
+        if (d.status != MD_OK) return d.status;
+        if (d.quick == 1) continue;
+        GDesc e;
+        memset(&e, 0, sizeof(e));
+        e.g = d.g;
+        e.prec = d.prec;
+        e.cs = d.cs;
+        const Lowering L = lower_case(d.cs);
+        if (d.quick == 2) {
+            e.kind = 1;
+            e.cfg = GCFG_64;
+            e.tiles_m = (int)((x.m + 63) / 64);
+            e.tiles_n = (int)((x.n + 63) / 64);
+        } else {
+            e.kind = 0;
+            const int64_t mr = x.m * (L.mdbl ? 2 : 1), nr = x.n * (L.ndbl ? 2 : 1);
+            e.cfg = choose_cfg(d.prec, d.cs, mr, nr);
+            const int edge = e.cfg == GCFG_64 ? 64 : 128;
+            const int64_t tmn_a = L.mdbl ? edge / 2 : edge, tmn_b = L.ndbl ? edge / 2 : edge;
+            e.tiles_m = (int)((x.m + tmn_a - 1) / tmn_a);
+            e.tiles_n = (int)((x.n + tmn_b - 1) / tmn_b);
+        }
+        const int di = (int)gd.size();
+        gd.push_back(e);
+        // estimated cost of one tile: its real-product flops, weighted by the
+        // computation precision's MFMA rate (FP64 is half FP32; BF16x3 ~1/2)
+        const int edge = e.kind == 1 ? 64 : (e.cfg == GCFG_64 ? 64 : 128);
+        const double kr = (double)x.k * (L.kdbl ? 2 : 1);
+        const double w = e.kind == 1 ? (double)edge * edge
+                                     : (double)edge * edge * kr * (d.prec == PREC_D ? 2.0 : (d.prec == PREC_S ? 1.0 : 0.5));
+        for (int tm = 0; tm < e.tiles_m; ++tm)
+            for (int tn = 0; tn < e.tiles_n; ++tn) {
+                tiles.push_back(GTile{di, tm, tn, 0});
+                work.push_back(w);
+            }
+    }
+    if (tiles.empty()) return MD_OK;
+    if (tiles.size() > 0x7fffffffu) return MD_ERR_UNSUPPORTED;
+    // Largest work first (LPT order) so the tail of the queue is short tiles.
+    std::vector<int> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+
+    const size_t hdr_bytes = 256;
+    const size_t desc_bytes = gd.size() * sizeof(GDesc);
+    const size_t tile_bytes = tiles.size() * sizeof(GTile);
+    const size_t total = hdr_bytes + desc_bytes + tile_bytes;
+    std::vector<char> host(total, 0);
+    memcpy(host.data() + hdr_bytes, gd.data(), desc_bytes);
+    GTile *ht = (GTile *)(host.data() + hdr_bytes + desc_bytes);
+    for (size_t i = 0; i < order.size(); ++i) ht[i] = tiles[order[i]];
+
+    hipStream_t s = (hipStream_t)stream;
+    char *dev = nullptr;
+    if (hipMallocAsync((void **)&dev, total, s) != hipSuccess) return MD_ERR_HIP;
+    if (hipMemcpyAsync(dev, host.data(), total, hipMemcpyHostToDevice, s) != hipSuccess) {
+        (void)hipFreeAsync(dev, s);
+        return MD_ERR_HIP;
+    }
+    const int ntiles = (int)tiles.size();
+    const int grid = std::min(ntiles, num_cu() * 2);
+    hipLaunchKernelGGL(md_grouped_kernel, dim3(grid), dim3(NT), 0, s, (const GDesc *)(dev + hdr_bytes),
+                       (const GTile *)(dev + hdr_bytes + desc_bytes), ntiles, (int *)dev);
+    const hipError_t le = hipGetLastError();
+    (void)hipFreeAsync(dev, s);
+    return le == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+// Tile-shape table file: one entry per line, "comp case bucket cfg" with comp
+// in {s, d, bf16x3}, case in {0, 1a, 1b, 1c, 2ab, 2ac, 2bc, 3}, bucket 0..5
+// (larger real-product dimension <= 64, 128, 256, 512, 1024, larger) and cfg
+// in {64, 128}; '#' starts a comment.  Entries not listed keep their value.
+int mdgemm_tune_load(const char *path) {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    default_table();
+    if (!path) return MD_OK;
+    FILE *f = fopen(path, "r");
+    if (!f) return MD_ERR_STATE;
+    static const char *cases[8] = {"0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3"};
+    int tmp[3][8][NBUCKET];
+    memcpy(tmp, g_table, sizeof(tmp));
+    char line[256];
+    int bad = 0;
+    while (fgets(line, sizeof(line), f)) {
+        char *h = strchr(line, '#');
+        if (h) *h = 0;
+        char comp[32], cs[32];
+        int bucket, cfg;
+        if (sscanf(line, "%31s %31s %d %d", comp, cs, &bucket, &cfg) != 4) {
+            if (sscanf(line, "%31s", comp) == 1) bad = 1;
+            continue;
+        }
+        int p = !strcmp(comp, "s") ? PREC_S : !strcmp(comp, "d") ? PREC_D : !strcmp(comp, "bf16x3") ? PREC_BF16X3 : -1;
+        int c = -1;
+        for (int i = 0; i < 8; ++i)
+            if (!strcmp(cs, cases[i])) c = i;
+        if (p < 0 || c < 0 || bucket < 0 || bucket >= NBUCKET || (cfg != 64 && cfg != 128) ||
+            (p == PREC_BF16X3 && cfg != 64)) {
+            bad = 1;
+            continue;
+        }
+        tmp[p][c][bucket] = cfg == 64 ? GCFG_64 : GCFG_128;
+    }
+    fclose(f);
+    if (bad) return MD_ERR_STATE;
+    memcpy(g_table, tmp, sizeof(tmp));
+    return MD_OK;
+}
+
+int mdgemm_tune_set(int comp, int domain_case, int bucket, int tile) {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    if (!g_table_init) default_table();
+    const int p = comp == MD_COMP_S ? PREC_S : comp == MD_COMP_D ? PREC_D : comp == MD_COMP_S_BF16X3 ? PREC_BF16X3 : -1;
+    if (p < 0 || domain_case < 0 || domain_case > 7 || bucket < 0 || bucket >= NBUCKET || (tile != 64 && tile != 128) ||
+        (p == PREC_BF16X3 && tile != 64))
+        return MD_ERR_STATE;
+    g_table[p][domain_case][bucket] = tile == 64 ? GCFG_64 : GCFG_128;
+    return MD_OK;
+}
+
+int mdgemm_tune_get(int comp, int domain_case, int bucket) {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    if (!g_table_init) default_table();
+    const int p = comp == MD_COMP_S ? PREC_S : comp == MD_COMP_D ? PREC_D : comp == MD_COMP_S_BF16X3 ? PREC_BF16X3 : -1;
+    if (p < 0 || domain_case < 0 || domain_case > 7 || bucket < 0 || bucket >= NBUCKET) return -1;
+    return g_table[p][domain_case][bucket] == GCFG_64 ? 64 : 128;
+}
+
+}  // extern "C"
