@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain copy kernel of known size (HBM counter calibration)")
+    p.add_argument("--check", action="store_true", help="grouped: check every product against the oracle")
     p.add_argument("--workload", default="sweep", choices=["sweep", "precision", "grouped", "serving"],
                    help="sweep: the 128-combination plain method at 4096 (default); precision: "
                         "FP32 vs BF16x3 at 8192; grouped: 512 mixed GEMMs in one launch; serving: "
@@ -302,6 +303,104 @@ def precision_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def grouped_workload(args):
+    """Batching form: 512 products, m, n, k each log-uniform integers in
+    [16, 1024], (storage combination, computation precision) uniform over the
+    128 cases, U[-1,1], alpha = beta = 1, fixed seed.  One grouped launch (tile
+    shapes from the autotuned table when present) against the same 512
+    products as back-to-back mdgemm calls on one stream."""
+    import torch
+    import oracle
+    from paper_1901_06015_amd import _lib, inputs
+    count = 512
+    dims = inputs.loguniform_dims(3 * count, 4242, 16, 1024).reshape(count, 3)
+    rng = np.random.Generator(np.random.PCG64(4243))
+    table = os.path.join(ROOT, "paper_1901_06015_amd", "tune_table.txt")
+    tuned = os.path.exists(table) and _lib.tune_load(table) == 0
+    if not tuned:
+        _lib.tune_load(None)
+    allc = combos("")
+    ents, keep, host = [], [], []
+    sp = torch.cuda.current_stream().cuda_stream
+    for i in range(count):
+        cabx = allc[int(rng.integers(0, len(allc)))]
+        m, n, k = (int(x) for x in dims[i])
+        tc, ta, tb, x = cabx
+        A = inputs.matrix(m, k, ta, 10 * i + 1)
+        B = inputs.matrix(k, n, tb, 10 * i + 2)
+        C = inputs.matrix(m, n, tc, 10 * i + 3)
+        dA, dB, dC = (torch.from_numpy(t).cuda() for t in (A, B, C))
+        ents.append((cabx, m, n, k))
+        keep.append((dA, dB, dC))
+        host.append((A, B, C))
+    def descs():
+        return [_lib.make_desc("N", "N", m, n, k, 1.0, dA.data_ptr(), c[1], m, dB.data_ptr(), c[2], k, 1.0,
+                               dC.data_ptr(), c[0], m, c[3]) for (c, m, n, k), (dA, dB, dC) in zip(ents, keep)]
+    D = descs()
+    flops = 0.0
+    roof = 0.0
+    for c, m, n, k in ents:
+        st, pl = _lib.mdgemm_plan("N", "N", m, n, k, 1.0, 1, c[1], m, 1, c[2], k, 1.0, 1, c[0], m, c[3])
+        flops += pl["flops"]
+        peak = (78.6 if c[3] == "d" else 157.3) * 1e12
+        byts = ELEM_BYTES[c[1]] * m * k + ELEM_BYTES[c[2]] * k * n + 2 * ELEM_BYTES[c[0]] * m * n
+        roof += max(pl["flops"] / peak, byts / 8e12)
+
+    def plain():
+        for (c, m, n, k), (dA, dB, dC) in zip(ents, keep):
+            st = _lib.mdgemm("N", "N", m, n, k, 1.0, dA.data_ptr(), c[1], m, dB.data_ptr(), c[2], k, 1.0,
+                             dC.data_ptr(), c[0], m, c[3], sp)
+            assert st == 0
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        return float(np.median(ts)), ts
+
+    print("# grouped: %d products, %.2f GFLOP" % (count, flops / 1e9), file=sys.stderr, flush=True)
+    tg, tgs = timed(lambda: _lib.mdgemm_grouped(D, sp), args.steps)
+    tp, tps = timed(plain, args.steps)
+    # correctness of one grouped launch on fresh C, every product against the oracle
+    for (dA, dB, dC), (A, B, C) in zip(keep, host):
+        dC.copy_(torch.from_numpy(C))
+    st = _lib.mdgemm_grouped(D, sp)
+    torch.cuda.synchronize()
+    o = oracle.get()
+    worst = 0.0
+    nchk = count if args.check else 16
+    for idx in range(nchk):
+        (c, m, n, k), (dA, dB, dC), (A, B, C) = ents[idx], keep[idx], host[idx]
+        st2, ref, g = o.gemm("N", "N", m, n, k, 1.0, A, c[1], m, B, c[2], k, 1.0, C, c[0], m)
+        got = dC.cpu().numpy().astype(np.complex128)
+        ux = 2.0 ** -24 if c[3] == "s" else 2.0 ** -53
+        uc = 2.0 ** -24 if c[0] in "sc" else 2.0 ** -53
+        bound = 4 * k * ux * g + 4 * uc * np.abs(ref)
+        worst = max(worst, float(np.max(np.abs(got - ref) / np.maximum(bound, 1e-300))))
+    line = {"metric": "GFLOP/s of 512 mixed GEMMs: one grouped launch vs one launch per GEMM",
+            "value": round(flops / tg / 1e9, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "batching form: 512 GEMMs, m,n,k log-uniform in [16,1024], 128 cases "
+                                   "uniform, U[-1,1], alpha=beta=1", "count": count,
+                       "tile_table": "autotuned" if tuned else "defaults"},
+            "total_gflop": round(flops / 1e9, 3),
+            "grouped_ms": round(tg * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
+            "plain_gflops": round(flops / tp / 1e9, 1),
+            "speedup_grouped_over_plain": round(tp / tg, 2),
+            "roofline": {"sum_of_per_gemm_roofline_ms": round(roof * 1e3, 3),
+                         "grouped_frac": round(roof / tg, 4), "plain_frac": round(roof / tp, 4)},
+            "max_err_over_bound": worst, "checked_products": nchk}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -310,6 +409,8 @@ def main():
         sys.exit(2)
     if args.workload == "precision":
         return precision_workload(args)
+    if args.workload == "grouped":
+        return grouped_workload(args)
     import torch
     from paper_1901_06015_amd import _lib, api
     _lib.lib()
