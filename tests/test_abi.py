@@ -127,3 +127,18 @@ def test_argument_errors():
 
 def test_grouped_empty_is_noop():
     assert _lib.mdgemm_grouped([], None) == 0
+
+
+def test_server_create_without_device_fails_cleanly():
+    """On a host without a GPU the serving loop refuses to start (no crash)."""
+    import torch
+    if torch.cuda.is_available():
+        import pytest
+        pytest.skip("a GPU is present")
+    from paper_1901_06015_amd.serving import Server, ServerError
+    try:
+        Server(budget_bytes=1 << 30)
+    except ServerError as e:
+        assert e.status == _lib.MD_ERR_HIP
+    else:
+        raise AssertionError("server started without a device")
