@@ -50,6 +50,16 @@ def parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain copy kernel of known size (HBM counter calibration)")
     p.add_argument("--check", action="store_true", help="grouped: check every product against the oracle")
+    p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of Poisson arrivals per stream")
+    p.add_argument("--qps", type=float, default=0.0,
+                   help="serving: offered requests/s (0: --load times the measured served capacity)")
+    p.add_argument("--load", type=float, default=0.7, help="serving: offered load as a fraction of capacity")
+    p.add_argument("--slots", type=int, default=4, help="serving: concurrent batches (streams)")
+    p.add_argument("--max-batch", type=int, default=64, help="serving: requests per grouped launch")
+    p.add_argument("--big-gflop", type=float, default=2.0, help="serving: requests above this run alone")
+    p.add_argument("--big-lanes", type=int, default=1, help="serving: large requests running at once")
+    p.add_argument("--no-plain-stream", action="store_true",
+                   help="serving: skip the plain-form run of the same arrival stream")
     p.add_argument("--workload", default="sweep", choices=["sweep", "precision", "grouped", "serving"],
                    help="sweep: the 128-combination plain method at 4096 (default); precision: "
                         "FP32 vs BF16x3 at 8192; grouped: 512 mixed GEMMs in one launch; serving: "
@@ -401,6 +411,267 @@ def grouped_workload(args):
     print(json.dumps(line), flush=True)
 
 
+class _ServingPool:
+    """Device-resident request templates for the serving form.
+
+    Small requests follow the batching form's distribution (m, n, k each a
+    log-uniform integer in [16, 1024], storage combination and computation
+    precision uniform over the 128 cases, U[-1,1], alpha = beta = 1), one
+    template per shape with its own A, B and input C.  Large requests are
+    m = n = k = 4096 in a uniformly drawn case; since they all share one
+    shape, one 4096 x 4096 operand per storage type serves as A, B or C of
+    every combination.  Templates are uploaded once (md_server_put) and every
+    request names them by handle."""
+
+    def __init__(self, srv, nsmall=1024, seed=5150, big=4096, host_cache=None):
+        import ctypes
+        from paper_1901_06015_amd import _lib, inputs, serving
+        self.srv, self.L = srv, srv.L
+        self.allc = combos("")
+        dims = inputs.loguniform_dims(3 * nsmall, seed, 16, 1024).reshape(nsmall, 3)
+        rng = np.random.Generator(np.random.PCG64(seed + 1))
+        self.small, self.small_flops = [], []
+        for i in range(nsmall):
+            cabx = self.allc[int(rng.integers(0, len(self.allc)))]
+            m, n, k = (int(x) for x in dims[i])
+            tc, ta, tb, x = cabx
+            ha = srv.put(inputs.matrix(m, k, ta, 10 * i + seed + 1))
+            hb = srv.put(inputs.matrix(k, n, tb, 10 * i + seed + 2))
+            hc = srv.put(inputs.matrix(m, n, tc, 10 * i + seed + 3))
+            self.small.append(dict(cabx=cabx, m=m, n=n, k=k, a=ha, b=hb, c=hc, seed=10 * i + seed))
+            st, pl = _lib.mdgemm_plan("N", "N", m, n, k, 1.0, 1, ta, m, 1, tb, k, 1.0, 1, tc, m, x)
+            self.small_flops.append(pl["flops"])
+        self.big_ops = {}
+        for j, t in enumerate("sdcz"):
+            for role in "abc":
+                key = (role, t, big, seed)
+                X = host_cache.get(key) if host_cache is not None else None
+                if X is None:
+                    X = inputs.matrix(big, big, t, seed + 100 + 3 * j + "abc".index(role))
+                    if host_cache is not None:
+                        host_cache[key] = X
+                self.big_ops[role + t] = srv.put(X)
+        self.big = big
+        self.big_tpl = [dict(cabx=c, m=big, n=big, k=big, a=self.big_ops["a" + c[1]], b=self.big_ops["b" + c[2]],
+                             c=self.big_ops["c" + c[0]]) for c in self.allc]
+        self.big_flops = []
+        for c in self.allc:
+            st, pl = _lib.mdgemm_plan("N", "N", big, big, big, 1.0, 1, c[1], big, 1, c[2], big, 1.0, 1, c[0],
+                                      big, c[3])
+            self.big_flops.append(pl["flops"])
+
+        def req(t, keep):
+            return serving.MdRequest(b"N", b"N", t["m"], t["n"], t["k"], _lib.scalar(1.0), t["a"], t["b"],
+                                     _lib.scalar(1.0), t["c"], _lib.tag(t["cabx"][0]), _lib.comp_tag(t["cabx"][3]),
+                                     1 if keep else 0)
+        self.small_req = [req(t, False) for t in self.small]
+        self.small_req_keep = [req(t, True) for t in self.small]
+        self.big_req = [req(t, False) for t in self.big_tpl]
+        self.ticket = ctypes.c_int64()
+
+    def draw(self, count, seed, big_frac=0.05):
+        """A seeded request sequence: (is_big, template index) per request."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        big = rng.random(count) < big_frac
+        si = rng.integers(0, len(self.small), count)
+        bi = rng.integers(0, len(self.big_tpl), count)
+        return [(bool(b), int(bb if b else s)) for b, s, bb in zip(big, si, bi)]
+
+    def flops_of(self, r):
+        return self.big_flops[r[1]] if r[0] else self.small_flops[r[1]]
+
+    def submit(self, srv, r, keep=False):
+        import ctypes
+        q = self.big_req[r[1]] if r[0] else (self.small_req_keep if keep else self.small_req)[r[1]]
+        st = self.L.md_server_submit(srv.h, ctypes.byref(q), ctypes.byref(self.ticket))
+        if st != 0:
+            raise RuntimeError("md_server_submit refused a benchmark request: %d" % st)
+        return self.ticket.value
+
+
+def _collect(srv, tickets, timeout):
+    """Wait for every ticket; returns arrays of (submit, admit, done) times in
+    microseconds and the batch sizes, then forgets the records."""
+    out = np.zeros((len(tickets), 4))
+    deadline = time.time() + timeout
+    for i, t in enumerate(tickets):
+        st, r = srv.wait(t, max(0.001, deadline - time.time()))
+        if st != 0 or r.status != 0:
+            raise RuntimeError("request %d did not complete (wait %d, status %d)" % (t, st, r.status))
+        out[i] = (r.t_submit_us, r.t_admit_us, r.t_done_us, r.batch_size)
+        srv.forget(t)
+    return out
+
+
+def _latency_stats(times, is_big, flops):
+    lat = (times[:, 2] - times[:, 0]) / 1e3
+    span = (times[:, 2].max() - times[:, 0].min()) / 1e6
+
+    def pct(x):
+        if len(x) == 0:
+            return None
+        return {"p50_ms": round(float(np.percentile(x, 50)), 3), "p99_ms": round(float(np.percentile(x, 99)), 3),
+                "mean_ms": round(float(np.mean(x)), 3), "count": int(len(x))}
+    return {"all": pct(lat), "small": pct(lat[~is_big]), "big_4096": pct(lat[is_big]),
+            "queue_wait_p99_ms": round(float(np.percentile((times[:, 1] - times[:, 0]) / 1e3, 99)), 3),
+            "mean_batch": round(float(np.mean(times[:, 3])), 2),
+            "sustained_gflops": round(float(np.sum(flops)) / span / 1e9, 1), "span_s": round(span, 3)}
+
+
+def _closed_loop(pool, srv, reqs):
+    tickets = [pool.submit(srv, r) for r in reqs]
+    times = _collect(srv, tickets, 600)
+    span = (times[:, 2].max() - times[:, 0].min()) / 1e6
+    fl = sum(pool.flops_of(r) for r in reqs)
+    return len(reqs) / span, fl / span / 1e9, span
+
+
+def _open_loop(pool, srv, reqs, arrivals, label, keep_first=0):
+    """Submit each request at its arrival time (busy-wait for the last
+    fraction of a millisecond), then wait for all of them."""
+    tickets, kept = [], []
+    t0 = time.perf_counter()
+    next_report = 10.0
+    late = 0.0
+    for i, (r, ta) in enumerate(zip(reqs, arrivals)):
+        target = t0 + ta
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            if target - now > 1e-3:
+                time.sleep(target - now - 5e-4)
+        late = max(late, now - target)
+        keep = (not r[0]) and len(kept) < keep_first
+        t = pool.submit(srv, r, keep=keep)
+        tickets.append(t)
+        if keep:
+            kept.append((i, t))
+        if ta >= next_report:
+            print("# %s: %.0f s, %d requests submitted" % (label, ta, i + 1), file=sys.stderr, flush=True)
+            next_report += 10.0
+    submit_s = time.perf_counter() - t0
+    outputs = []
+    for i, t in kept:
+        st, res = srv.wait(t, 600)
+        outputs.append((i, res.output))
+    times = _collect(srv, tickets, 3 * max(60.0, arrivals[-1]))
+    return times, submit_s, late, outputs
+
+
+def serving_workload(args):
+    """Serving form: a Poisson stream of requests at a fixed rate (by default
+    70 % of the measured served capacity) for --duration seconds; each request
+    is drawn from the batching form's distribution, or with probability 0.05
+    is an m = n = k = 4096 product of a uniformly drawn case.  Admission is
+    capped by a 64 GB in-flight working-set budget.  The plain form is the
+    same server with batching and overlap off (one stream slot, every request
+    its own mdgemm, in arrival order).  Reported: both forms' closed-loop
+    capacity, the served form's latency at --load of its capacity, and both
+    forms' latency on one stream at --load of the plain form's capacity.
+    Latency = completion observed by the server minus submission."""
+    import torch
+    import oracle
+    from paper_1901_06015_amd import _lib, inputs, serving
+    _lib.lib()
+    torch.cuda.set_device(0)
+    torch.cuda.init()
+    table = os.path.join(ROOT, "paper_1901_06015_amd", "tune_table.txt")
+    tuned = os.path.exists(table) and _lib.tune_load(table) == 0
+    budget = 64 << 30
+    big_flops = args.big_gflop * 1e9
+    srv = serving.Server(budget, slots=args.slots, max_batch=args.max_batch, big_flops=big_flops,
+                         big_lanes=args.big_lanes)
+    plain = None if args.no_plain_stream else serving.Server(budget, slots=1, max_batch=1, big_flops=0.0)
+    t0 = time.time()
+    cache = {}
+    pool = _ServingPool(srv, host_cache=cache)
+    # the plain-form server holds its own copies of the same templates
+    ppool = _ServingPool(plain, host_cache=cache) if not args.no_plain_stream else None
+    cache.clear()
+    print("# serving: templates resident in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+
+    # closed-loop capacity of both forms on one seeded sample (after a warm-up)
+    sample = pool.draw(2000, 6001)
+    _closed_loop(pool, srv, pool.draw(300, 6000))
+    cap_rps, cap_gf, cap_span = _closed_loop(pool, srv, sample)
+    print("# serving capacity: %.0f req/s, %.0f GFLOP/s" % (cap_rps, cap_gf), file=sys.stderr, flush=True)
+    pcap = None
+    if ppool is not None:
+        _closed_loop(ppool, plain, ppool.draw(300, 6000))
+        p_rps, p_gf, p_span = _closed_loop(ppool, plain, sample)
+        pcap = {"req_per_s": round(p_rps, 1), "gflops": round(p_gf, 1)}
+        print("# plain capacity: %.0f req/s, %.0f GFLOP/s" % (p_rps, p_gf), file=sys.stderr, flush=True)
+
+    def stream(qps, seed):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        nreq = int(np.ceil(qps * args.duration * 1.2)) + 16
+        arr = np.cumsum(rng.exponential(1.0 / qps, nreq))
+        arr = arr[arr < args.duration]
+        rq = pool.draw(len(arr), seed + 1)
+        return arr, rq, np.array([r[0] for r in rq]), np.array([pool.flops_of(r) for r in rq])
+
+    # headline: the served form at --load of its own capacity
+    qps = args.qps if args.qps > 0 else args.load * cap_rps
+    arrivals, reqs, is_big, flops = stream(qps, 6002)
+    print("# serving stream: %d requests over %.0f s at %.0f req/s" % (len(reqs), args.duration, qps),
+          file=sys.stderr, flush=True)
+    times, submit_s, late, outputs = _open_loop(pool, srv, reqs, arrivals, "served", keep_first=8)
+    served = _latency_stats(times, is_big, flops)
+    served["offered_req_per_s"] = round(qps, 1)
+    served["submit_lag_max_ms"] = round(late * 1e3, 3)
+    counters = srv.stats()
+
+    # the kept outputs against the oracle (elementwise bound)
+    o = oracle.get()
+    worst = 0.0
+    for i, h in outputs:
+        t = pool.small[reqs[i][1]]
+        tc, ta, tb, x = t["cabx"]
+        m, n, k, sd = t["m"], t["n"], t["k"], t["seed"]
+        A, B, C = inputs.matrix(m, k, ta, sd + 1), inputs.matrix(k, n, tb, sd + 2), inputs.matrix(m, n, tc, sd + 3)
+        st, ref, g = o.gemm("N", "N", m, n, k, 1.0, A, ta, m, B, tb, k, 1.0, C, tc, m)
+        got = srv.fetch(h, m, n, tc).astype(np.complex128)
+        srv.drop(h)
+        ux = 2.0 ** -24 if x == "s" else 2.0 ** -53
+        uc = 2.0 ** -24 if tc in "sc" else 2.0 ** -53
+        bound = 4 * k * ux * g + 4 * uc * np.abs(ref)
+        worst = max(worst, float(np.max(np.abs(got - ref) / np.maximum(bound, 1e-300))))
+
+    # both forms at one rate the plain form can sustain (--load of its capacity)
+    equal = None
+    if ppool is not None:
+        q2 = args.load * pcap["req_per_s"]
+        arr2, req2, big2, fl2 = stream(q2, 6004)
+        print("# equal-rate streams: %d requests at %.0f req/s" % (len(req2), q2), file=sys.stderr, flush=True)
+        t_s, _, lag_s, _ = _open_loop(pool, srv, req2, arr2, "served@equal")
+        t_p, _, lag_p, _ = _open_loop(ppool, plain, req2, arr2, "plain@equal")
+        equal = {"offered_req_per_s": round(q2, 1), "requests": len(req2),
+                 "served": _latency_stats(t_s, big2, fl2), "plain": _latency_stats(t_p, big2, fl2)}
+        plain.close()
+    srv.close()
+
+    line = {"metric": "served mixed GEMM: sustained GFLOP/s and p50/p99 latency under a Poisson stream",
+            "value": served["sustained_gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": "serving form: Poisson arrivals for %.0f s; 95%% batching-form requests "
+                                   "(m,n,k log-uniform in [16,1024], 128 cases uniform), 5%% m=n=k=4096 of a "
+                                   "uniform case; U[-1,1], alpha=beta=1; 64 GB working-set budget"
+                                   % args.duration,
+                       "offered_req_per_s": round(qps, 1), "requests": len(reqs),
+                       "big_fraction": round(float(is_big.mean()), 4), "slots": args.slots,
+                       "max_batch": args.max_batch, "big_gflop": args.big_gflop, "big_lanes": args.big_lanes,
+                       "tile_table": "autotuned" if tuned else "defaults", "budget_bytes": budget},
+            "latency": served, "equal_rate": equal,
+            "capacity": {"served": {"req_per_s": round(cap_rps, 1), "gflops": round(cap_gf, 1)}, "plain": pcap},
+            "counters": {k: counters[k] for k in ("batches", "grouped_launches", "plain_launches",
+                                                  "peak_inflight_bytes", "max_concurrent_batches",
+                                                  "resident_bytes", "pool_bytes", "device_mallocs")},
+            "max_err_over_bound": worst, "checked_outputs": len(outputs)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -411,6 +682,8 @@ def main():
         return precision_workload(args)
     if args.workload == "grouped":
         return grouped_workload(args)
+    if args.workload == "serving":
+        return serving_workload(args)
     import torch
     from paper_1901_06015_amd import _lib, api
     _lib.lib()

@@ -55,6 +55,8 @@ struct GemmArgs {
     const void *A;
     const void *B;
     void *C;
+    const void *Cin;        // where beta*C is read from: C itself for the in-place
+                            // operation, another m x n array of C's type and ldc otherwise
     int64_t lda, ldb, ldc;  // in elements of each operand's own type
     int64_t m, n, k;
     int a_dbl, b_dbl, c_dbl;  // storage precision is double
@@ -87,5 +89,23 @@ int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_o
 int launch_scale(const GemmArgs &a, void *stream);
 void tile_shape(int prec, int cs, int *bm, int *bn, int *bk);
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len);
+
+// Out-of-place forms used by the serving loop of the same library:
+// C := beta*Cin + alpha*op(A)op(B), where Cin (m x n, C's storage type,
+// leading dimension ldc) is read and C is written; a null c_in means in place.
+// Validation and status codes are mdgemm's / mdgemm_grouped's.
+int gemm_enqueue(const md_gemm_desc &d, const void *c_in, void *stream);
+
+// Reusable descriptor-table workspace of one stream that issues grouped
+// launches: page-locked host staging and its device copy, grown on demand.
+// The caller guarantees that the launch which last used it has completed.
+struct GroupedWs {
+    char *host = nullptr;
+    char *dev = nullptr;
+    size_t cap = 0;
+};
+int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const *c_in, void *stream,
+                    GroupedWs *ws);
+void grouped_ws_release(GroupedWs *ws);
 
 }  // namespace md

@@ -1,8 +1,8 @@
 // md_server.cpp -- request loop with continuous batching under an HBM budget
 // (include/md_server.h).  One scheduler thread owns all device work: it
-// retires finished batches (event queries), admits queued requests in arrival
-// order while a slot and budget are free, and launches each batch on its
-// slot's stream.  Clients only touch the queue and the result records.
+// retires finished batches (event queries), admits queued requests while a
+// slot and budget are free, and launches each batch on its slot's stream.
+// Clients only touch the queues, the operand table and the result records.
 #include <hip/hip_runtime_api.h>
 #include <stdio.h>
 #include <string.h>
@@ -10,6 +10,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -22,29 +23,101 @@ namespace {
 
 int elem_bytes(int dt) { return dt == MD_S ? 4 : (dt == MD_Z ? 16 : 8); }
 
+// Size class of a device block: 4 KiB minimum, then four classes per power of
+// two, so a block wastes less than a quarter of its size.
+int64_t size_class(int64_t b) {
+    if (b <= 4096) return 4096;
+    const int e = 63 - __builtin_clzll((unsigned long long)(b - 1));  // 2^e < b <= 2^(e+1)
+    const int64_t step = (int64_t)1 << (e - 2);
+    return (b + step - 1) / step * step;
+}
+
+// Device allocator of the server: free lists per size class.  A block comes
+// back to its list only when no queued or running request can touch it (the
+// scheduler returns outputs after their batch's event has completed), so it
+// can be handed out again at once.  The cache is trimmed when it holds more
+// than `limit` bytes.
+class DevicePool {
+  public:
+    explicit DevicePool(int64_t limit) : limit_(limit) {}
+
+    void *get(int64_t bytes, int64_t *cls) {
+        const int64_t c = size_class(bytes);
+        *cls = c;
+        auto it = free_.find(c);
+        if (it != free_.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            cached_ -= c;
+            return p;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)c) != hipSuccess) {
+            // release the cache and try once more
+            trim(0);
+            if (hipMalloc(&p, (size_t)c) != hipSuccess) return nullptr;
+        }
+        held_ += c;
+        mallocs_++;
+        return p;
+    }
+
+    void put(void *p, int64_t cls) {
+        if (!p) return;
+        free_[cls].push_back(p);
+        cached_ += cls;
+        if (cached_ > limit_) trim(limit_ / 2);
+    }
+
+    void release_all() { trim(0); }
+
+    int64_t held() const { return held_; }
+    int64_t mallocs() const { return mallocs_; }
+
+  private:
+    void trim(int64_t keep) {
+        // largest classes first
+        for (auto it = free_.rbegin(); it != free_.rend() && cached_ > keep; ++it) {
+            while (!it->second.empty() && cached_ > keep) {
+                (void)hipFree(it->second.back());
+                it->second.pop_back();
+                cached_ -= it->first;
+                held_ -= it->first;
+            }
+        }
+    }
+
+    std::map<int64_t, std::vector<void *>> free_;
+    int64_t limit_, cached_ = 0, held_ = 0, mallocs_ = 0;
+};
+
 struct Operand {
     void *ptr = nullptr;
+    int64_t cls = 0;  // allocator size class of ptr
     int dt = 0;
     int64_t rows = 0, cols = 0;
     int64_t bytes = 0;
-    int users = 0;  // queued or running requests that read it
+    int users = 0;  // queued or running requests (and fetches) that read it
 };
 
 struct Req {
     md_request r;
     int64_t id = 0;
-    int64_t ws = 0;  // working-set bytes: A + B + output C
+    int64_t ws = 0;  // working-set bytes: A + B + input C + output C
     double flops = 0;
     bool big = false;
     md_result res{};
     void *out = nullptr;
+    int64_t out_cls = 0;
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     std::vector<Req *> batch;
+    md::GroupedWs ws;
     bool busy = false;
+    bool big = false;
 };
 
 }  // namespace
@@ -52,7 +125,7 @@ struct Slot {
 struct md_server {
     std::mutex mu;
     std::condition_variable cv_sched, cv_done;
-    std::deque<Req *> pending;
+    std::deque<Req *> smallq, bigq;
     std::unordered_map<int64_t, Req *> reqs;
     std::unordered_map<int64_t, Operand> ops;
     std::vector<Slot> slots;
@@ -60,11 +133,16 @@ struct md_server {
     bool stop = false;
     int device = 0;
     int64_t budget = 0, inflight = 0, peak = 0, resident = 0;
-    int max_batch = 1;
+    int max_batch = 1, big_lanes = 1, big_running = 0;
     double big_flops = 0;
     int64_t next_id = 1, next_handle = 1;
     md_server_counters st{};
+    DevicePool pool;
+    std::vector<md_gemm_desc> descs;
+    std::vector<const void *> cins;
     std::chrono::steady_clock::time_point t0;
+
+    explicit md_server(int64_t budget_bytes) : pool(budget_bytes) {}
 
     double now_us() const {
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -76,9 +154,11 @@ struct md_server {
 };
 
 void md_server::retire_locked() {
+    bool any = false;
     for (auto &sl : slots) {
         if (!sl.busy) continue;
         if (hipEventQuery(sl.done) != hipSuccess) continue;
+        any = true;
         const double t = now_us();
         for (Req *q : sl.batch) {
             q->res.done = 1;
@@ -88,9 +168,10 @@ void md_server::retire_locked() {
                 auto it = ops.find(h);
                 if (it != ops.end()) it->second.users--;
             }
-            if (q->res.status == MD_OK && q->r.keep_output) {
+            if (q->res.status == MD_OK && q->r.keep_output && q->out) {
                 Operand o;
                 o.ptr = q->out;
+                o.cls = q->out_cls;
                 o.dt = q->r.dtc;
                 o.rows = q->r.m;
                 o.cols = q->r.n;
@@ -99,41 +180,36 @@ void md_server::retire_locked() {
                 ops[h] = o;
                 resident += o.bytes;
                 q->res.output = h;
-            } else if (q->out) {
-                (void)hipFreeAsync(q->out, sl.stream);
+            } else {
+                pool.put(q->out, q->out_cls);
             }
             q->out = nullptr;
             st.completed++;
         }
+        if (sl.big) big_running--;
         sl.batch.clear();
         sl.busy = false;
+        sl.big = false;
     }
-    cv_done.notify_all();
+    if (any) cv_done.notify_all();
 }
 
 void md_server::launch_locked(Slot &sl) {
     const double t = now_us();
-    std::vector<md_gemm_desc> descs;
+    descs.clear();
+    cins.clear();
     int err = MD_OK;
     for (Req *q : sl.batch) {
         q->res.t_admit_us = t;
         q->res.batch_size = (int)sl.batch.size();
         const int64_t cb = q->r.m * q->r.n * elem_bytes(q->r.dtc);
-        if (hipMallocAsync(&q->out, cb > 0 ? cb : 1, sl.stream) != hipSuccess) {
-            q->out = nullptr;
+        q->out = pool.get(cb > 0 ? cb : 1, &q->out_cls);
+        if (!q->out) {
             q->res.status = MD_ERR_HIP;
             err = MD_ERR_HIP;
             continue;
         }
         const bool use_c = (q->r.beta.re != 0.0 || q->r.beta.im != 0.0) && q->r.c_in >= 0;
-        if (use_c) {
-            const Operand &c = ops[q->r.c_in];
-            if (hipMemcpyAsync(q->out, c.ptr, cb, hipMemcpyDeviceToDevice, sl.stream) != hipSuccess) {
-                q->res.status = MD_ERR_HIP;
-                err = MD_ERR_HIP;
-                continue;
-            }
-        }
         const Operand &A = ops[q->r.a], &B = ops[q->r.b];
         md_gemm_desc d;
         d.transa = q->r.transa;
@@ -154,16 +230,16 @@ void md_server::launch_locked(Slot &sl) {
         d.ldc = q->r.m > 0 ? q->r.m : 1;
         d.comp = q->r.comp;
         descs.push_back(d);
+        // beta*C is read from the resident input, the result written to the fresh output
+        cins.push_back(use_c ? ops[q->r.c_in].ptr : nullptr);
     }
     if (err == MD_OK) {
         int rc;
-        if (sl.batch.size() == 1 && sl.batch[0]->big) {
-            const md_gemm_desc &d = descs[0];
-            rc = mdgemm(d.transa, d.transb, d.m, d.n, d.k, d.alpha, d.A, d.dta, d.lda, d.B, d.dtb, d.ldb, d.beta,
-                        d.C, d.dtc, d.ldc, d.comp, sl.stream);
+        if (sl.big) {
+            rc = md::gemm_enqueue(descs[0], cins[0], sl.stream);
             st.plain_launches++;
         } else {
-            rc = mdgemm_grouped((int64_t)descs.size(), descs.data(), sl.stream);
+            rc = md::grouped_enqueue((int64_t)descs.size(), descs.data(), cins.data(), sl.stream, &sl.ws);
             st.grouped_launches++;
         }
         if (rc != MD_OK)
@@ -179,21 +255,35 @@ void md_server::launch_locked(Slot &sl) {
 
 void md_server::admit_locked() {
     for (auto &sl : slots) {
-        if (sl.busy || pending.empty()) continue;
-        // take requests in arrival order while they fit the budget; a large
-        // request runs alone
-        while (!pending.empty() && (int)sl.batch.size() < max_batch) {
-            Req *q = pending.front();
-            if (inflight + q->ws > budget) break;
-            if (q->big && !sl.batch.empty()) break;
-            pending.pop_front();
+        if (sl.busy) continue;
+        if (smallq.empty() && bigq.empty()) break;
+        auto take = [&](Req *q) {
             inflight += q->ws;
             if (inflight > peak) peak = inflight;
             sl.batch.push_back(q);
             st.admitted++;
-            if (q->big) break;
+        };
+        // the oldest large request first, when a lane is free
+        int64_t held_back = INT64_MAX;  // small requests that arrived after this id wait
+        if (!bigq.empty() && big_running < big_lanes) {
+            Req *q = bigq.front();
+            if (inflight + q->ws <= budget) {
+                bigq.pop_front();
+                take(q);
+                sl.big = true;
+                big_running++;
+                launch_locked(sl);
+                continue;
+            }
+            held_back = q->id;
         }
-        if (sl.batch.empty()) break;  // the head does not fit: wait for completions
+        while (!smallq.empty() && (int)sl.batch.size() < max_batch) {
+            Req *q = smallq.front();
+            if (q->id > held_back || inflight + q->ws > budget) break;
+            smallq.pop_front();
+            take(q);
+        }
+        if (sl.batch.empty()) break;  // nothing fits: wait for completions
         launch_locked(sl);
     }
 }
@@ -206,31 +296,34 @@ void md_server::run() {
         admit_locked();
         bool busy = false;
         for (auto &sl : slots) busy |= sl.busy;
-        if (stop && !busy && pending.empty()) break;
+        if (stop && !busy && smallq.empty() && bigq.empty()) break;
         if (busy) {
             // device work in flight: poll its events at a fine interval
             cv_sched.wait_for(lk, std::chrono::microseconds(20));
         } else {
-            cv_sched.wait(lk, [&] { return stop || !pending.empty(); });
+            cv_sched.wait(lk, [&] { return stop || !smallq.empty() || !bigq.empty(); });
         }
     }
 }
 
 extern "C" {
 
-int md_server_create(int64_t budget_bytes, int slots, int max_batch, double big_flops, md_server **out) {
+int md_server_create(const md_server_config *cfg, md_server **out) {
     if (!out) return MD_ERR_STATE;
     *out = nullptr;
-    if (budget_bytes <= 0 || slots <= 0 || max_batch <= 0) return MD_ERR_STATE;
+    if (!cfg || cfg->budget_bytes <= 0 || cfg->slots <= 0 || cfg->max_batch <= 0 || cfg->big_lanes < 1 ||
+        cfg->big_lanes > cfg->slots)
+        return MD_ERR_STATE;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return MD_ERR_HIP;
-    md_server *s = new md_server();
+    md_server *s = new md_server(cfg->budget_bytes);
     s->device = dev;
-    s->budget = budget_bytes;
-    s->max_batch = max_batch;
-    s->big_flops = big_flops;
+    s->budget = cfg->budget_bytes;
+    s->max_batch = cfg->max_batch;
+    s->big_flops = cfg->big_flops;
+    s->big_lanes = cfg->big_lanes;
     s->t0 = std::chrono::steady_clock::now();
-    s->slots.resize(slots);
+    s->slots.resize(cfg->slots);
     for (auto &sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
@@ -242,7 +335,7 @@ int md_server_create(int64_t budget_bytes, int slots, int max_batch, double big_
             return MD_ERR_HIP;
         }
     }
-    s->st.budget_bytes = budget_bytes;
+    s->st.budget_bytes = cfg->budget_bytes;
     s->sched = std::thread([s] { s->run(); });
     *out = s;
     return MD_OK;
@@ -259,7 +352,9 @@ int md_server_destroy(md_server *s) {
     for (auto &sl : s->slots) (void)hipStreamSynchronize(sl.stream);
     for (auto &kv : s->ops) (void)hipFree(kv.second.ptr);
     for (auto &kv : s->reqs) delete kv.second;
+    s->pool.release_all();
     for (auto &sl : s->slots) {
+        md::grouped_ws_release(&sl.ws);
         (void)hipEventDestroy(sl.done);
         (void)hipStreamDestroy(sl.stream);
     }
@@ -274,9 +369,14 @@ int md_server_put(md_server *s, const void *host, md_dt dt, int64_t rows, int64_
     o.rows = rows;
     o.cols = cols;
     o.bytes = rows * cols * elem_bytes(dt);
-    if (hipMalloc(&o.ptr, o.bytes > 0 ? o.bytes : 1) != hipSuccess) return MD_ERR_HIP;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        o.ptr = s->pool.get(o.bytes > 0 ? o.bytes : 1, &o.cls);
+    }
+    if (!o.ptr) return MD_ERR_HIP;
     if (o.bytes > 0 && hipMemcpy(o.ptr, host, o.bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(o.ptr);
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->pool.put(o.ptr, o.cls);
         return MD_ERR_HIP;
     }
     std::lock_guard<std::mutex> lk(s->mu);
@@ -288,16 +388,12 @@ int md_server_put(md_server *s, const void *host, md_dt dt, int64_t rows, int64_
 
 int md_server_drop(md_server *s, int64_t handle) {
     if (!s) return MD_ERR_STATE;
-    void *p = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        auto it = s->ops.find(handle);
-        if (it == s->ops.end() || it->second.users > 0) return MD_ERR_STATE;
-        p = it->second.ptr;
-        s->resident -= it->second.bytes;
-        s->ops.erase(it);
-    }
-    (void)hipFree(p);
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->ops.find(handle);
+    if (it == s->ops.end() || it->second.users > 0) return MD_ERR_STATE;
+    s->resident -= it->second.bytes;
+    s->pool.put(it->second.ptr, it->second.cls);
+    s->ops.erase(it);
     return MD_OK;
 }
 
@@ -309,9 +405,12 @@ int md_server_fetch(md_server *s, int64_t handle, void *host) {
         auto it = s->ops.find(handle);
         if (it == s->ops.end()) return MD_ERR_STATE;
         o = it->second;
+        it->second.users++;  // not dropped while the copy runs
     }
-    if (o.bytes > 0 && hipMemcpy(host, o.ptr, o.bytes, hipMemcpyDeviceToHost) != hipSuccess) return MD_ERR_HIP;
-    return MD_OK;
+    const bool ok = o.bytes == 0 || hipMemcpy(host, o.ptr, o.bytes, hipMemcpyDeviceToHost) == hipSuccess;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->ops[handle].users--;
+    return ok ? MD_OK : MD_ERR_HIP;
 }
 
 int md_server_submit(md_server *s, const md_request *r, int64_t *ticket) {
@@ -358,7 +457,8 @@ int md_server_submit(md_server *s, const md_request *r, int64_t *ticket) {
     q->id = s->next_id++;
     q->flops = p.flops;
     q->big = p.flops > s->big_flops;
-    q->ws = A.bytes + B.bytes + r->m * r->n * elem_bytes(r->dtc);
+    const int64_t cb = r->m * r->n * elem_bytes(r->dtc);
+    q->ws = A.bytes + B.bytes + cb + (beta0 ? 0 : cb);
     if (q->ws > s->budget) {
         s->st.refused++;
         delete q;
@@ -375,7 +475,7 @@ int md_server_submit(md_server *s, const md_request *r, int64_t *ticket) {
     }
     if (beta0) q->r.c_in = -1;
     s->reqs[q->id] = q;
-    s->pending.push_back(q);
+    (q->big ? s->bigq : s->smallq).push_back(q);
     *ticket = q->id;
     lk.unlock();
     s->cv_sched.notify_one();
@@ -420,6 +520,8 @@ int md_server_stats(md_server *s, md_server_counters *out) {
     out->peak_inflight_bytes = s->peak;
     out->resident_bytes = s->resident;
     out->budget_bytes = s->budget;
+    out->pool_bytes = s->pool.held();
+    out->device_mallocs = s->pool.mallocs();
     return MD_OK;
 }
 

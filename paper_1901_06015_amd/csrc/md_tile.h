@@ -334,24 +334,26 @@ __device__ __forceinline__ void update_real(const GemmArgs &g, int64_t i, int64_
     const T ax = (T)g.alpha_re;
     if (g.c_dbl) {
         double *c = (double *)g.C;
+        const double *cin = (const double *)g.Cin;
         const double t = (double)ax * (double)acc;
-        c[off] = g.beta_zero ? t : fma(g.beta_re, c[off], t);
+        c[off] = g.beta_zero ? t : fma(g.beta_re, cin[off], t);
     } else {
         float *c = (float *)g.C;
+        const float *cin = (const float *)g.Cin;
         const float bc = (float)g.beta_re;
         if constexpr (sizeof(T) == 8) {
             const double t = ax * acc;
-            c[off] = (float)(g.beta_zero ? t : fma((double)bc, (double)c[off], t));
+            c[off] = (float)(g.beta_zero ? t : fma((double)bc, (double)cin[off], t));
         } else {
             const float t = ax * acc;
-            c[off] = g.beta_zero ? t : fmaf(bc, c[off], t);
+            c[off] = g.beta_zero ? t : fmaf(bc, cin[off], t);
         }
     }
 }
 
 // Complex C: (re, im) is alpha-free AB for this element (im == 0 in case 1c).
 template <class T, class W>
-__device__ __forceinline__ void cupdate(const GemmArgs &g, W *c2, W re, W im, W ar, W ai) {
+__device__ __forceinline__ void cupdate(const GemmArgs &g, W *c2, const W *cin2, W re, W im, W ar, W ai) {
     const W tr = fma(ar, re, -(ai * im));
     const W ti = fma(ar, im, ai * re);
     if (g.beta_zero) {
@@ -359,7 +361,7 @@ __device__ __forceinline__ void cupdate(const GemmArgs &g, W *c2, W re, W im, W 
         c2[1] = ti;
     } else {
         const W br = (W)g.beta_re, bi = (W)g.beta_im;
-        const W cr = c2[0], ci = c2[1];
+        const W cr = cin2[0], ci = cin2[1];
         c2[0] = fma(br, cr, fma(-bi, ci, tr));
         c2[1] = fma(br, ci, fma(bi, cr, ti));
     }
@@ -373,16 +375,17 @@ __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_
     if (g.c_dbl) {
         double *c = (double *)g.C + off;
         // beta is already double (C's precision); product in double.
-        cupdate<T, double>(g, c, (double)re, (double)im, (double)ar, (double)ai);
+        cupdate<T, double>(g, c, (const double *)g.Cin + off, (double)re, (double)im, (double)ar, (double)ai);
     } else if constexpr (sizeof(T) == 8) {
         // computation in double, C single: beta cast to single, update in double
         float *c = (float *)g.C + off;
+        const float *cin = (const float *)g.Cin + off;
         const double br = (double)(float)g.beta_re, bi = (double)(float)g.beta_im;
         const double tr = fma(ar, re, -(ai * im));
         const double ti = fma(ar, im, ai * re);
         double rr = tr, ri = ti;
         if (!g.beta_zero) {
-            const double cr = c[0], ci = c[1];
+            const double cr = cin[0], ci = cin[1];
             rr = fma(br, cr, fma(-bi, ci, tr));
             ri = fma(br, ci, fma(bi, cr, ti));
         }
@@ -390,7 +393,7 @@ __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_
         c[1] = (float)ri;
     } else {
         float *c = (float *)g.C + off;
-        cupdate<T, float>(g, c, re, im, ar, ai);
+        cupdate<T, float>(g, c, (const float *)g.Cin + off, re, im, ar, ai);
     }
 }
 

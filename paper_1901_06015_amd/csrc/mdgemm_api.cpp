@@ -74,7 +74,7 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     if (!dt_dbl(dtc)) { bre = (double)(float)bre; bim = (double)(float)bim; }
 
     GemmArgs &g = d.g;
-    g.A = A; g.B = B; g.C = C;
+    g.A = A; g.B = B; g.C = C; g.Cin = C;
     g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.m = m; g.n = n; g.k = k;
     g.a_dbl = dt_dbl(dta); g.b_dbl = dt_dbl(dtb); g.c_dbl = dt_dbl(dtc);
@@ -109,18 +109,37 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
 
 }  // namespace md
 
-extern "C" {
+namespace {
 
-int mdgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
-           const void *A, md_dt dta, int64_t lda, const void *B, md_dt dtb, int64_t ldb,
-           md_scalar beta, void *C, md_dt dtc, int64_t ldc, md_comp comp, void *stream) {
-    Decision d = decide(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C, dtc,
-                        ldc, comp);
+int run_decision(const Decision &d, void *stream) {
     if (d.status != MD_OK) return d.status;
     if (d.quick == 1) return MD_OK;
     if (d.quick == 2) return launch_scale(d.g, stream);
     if ((int64_t)d.g.tiles_m * d.g.tiles_n > 0x7fffffffLL) return MD_ERR_UNSUPPORTED;
     return launch_gemm(d.prec, d.cs, d.g, stream, nullptr);
+}
+
+}  // namespace
+
+namespace md {
+
+int gemm_enqueue(const md_gemm_desc &x, const void *c_in, void *stream) {
+    Decision d = decide(x.transa, x.transb, x.m, x.n, x.k, x.alpha, x.A, x.dta, x.lda, x.B, x.dtb, x.ldb,
+                        x.beta, x.C, x.dtc, x.ldc, x.comp);
+    if (c_in) d.g.Cin = c_in;
+    return run_decision(d, stream);
+}
+
+}  // namespace md
+
+extern "C" {
+
+int mdgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
+           const void *A, md_dt dta, int64_t lda, const void *B, md_dt dtb, int64_t ldb,
+           md_scalar beta, void *C, md_dt dtc, int64_t ldc, md_comp comp, void *stream) {
+    const Decision d = decide(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C, dtc,
+                              ldc, comp);
+    return run_decision(d, stream);
 }
 
 int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,

@@ -58,9 +58,10 @@ int num_cu() {
 
 using namespace md;
 
-extern "C" {
+namespace md {
 
-int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
+int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const *c_in, void *stream,
+                    GroupedWs *ws) {
     if (count < 0) return -1;
     if (count == 0) return MD_OK;
     if (!descs) return -2;
@@ -78,6 +79,7 @@ int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
         GDesc e;
         memset(&e, 0, sizeof(e));
         e.g = d.g;
+        if (c_in && c_in[i]) e.g.Cin = c_in[i];
         e.prec = d.prec;
         e.cs = d.cs;
         const Lowering L = lower_case(d.cs);
@@ -120,16 +122,39 @@ int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
     const size_t desc_bytes = gd.size() * sizeof(GDesc);
     const size_t tile_bytes = tiles.size() * sizeof(GTile);
     const size_t total = hdr_bytes + desc_bytes + tile_bytes;
-    std::vector<char> host(total, 0);
-    memcpy(host.data() + hdr_bytes, gd.data(), desc_bytes);
-    GTile *ht = (GTile *)(host.data() + hdr_bytes + desc_bytes);
-    for (size_t i = 0; i < order.size(); ++i) ht[i] = tiles[order[i]];
-
     hipStream_t s = (hipStream_t)stream;
-    char *dev = nullptr;
-    if (hipMallocAsync((void **)&dev, total, s) != hipSuccess) return MD_ERR_HIP;
-    if (hipMemcpyAsync(dev, host.data(), total, hipMemcpyHostToDevice, s) != hipSuccess) {
-        (void)hipFreeAsync(dev, s);
+    std::vector<char> tmp;
+    char *host = nullptr, *dev = nullptr;
+    if (ws) {
+        // grow the reusable staging: the launch that used it has completed
+        if (ws->cap < total) {
+            grouped_ws_release(ws);
+            const size_t cap = std::max<size_t>(total + total / 2, 1 << 20);
+            if (hipHostMalloc((void **)&ws->host, cap, hipHostMallocDefault) != hipSuccess) {
+                ws->host = nullptr;
+                return MD_ERR_HIP;
+            }
+            if (hipMalloc((void **)&ws->dev, cap) != hipSuccess) {
+                (void)hipHostFree(ws->host);
+                ws->host = nullptr;
+                ws->dev = nullptr;
+                return MD_ERR_HIP;
+            }
+            ws->cap = cap;
+        }
+        host = ws->host;
+        dev = ws->dev;
+    } else {
+        tmp.resize(total);
+        host = tmp.data();
+        if (hipMallocAsync((void **)&dev, total, s) != hipSuccess) return MD_ERR_HIP;
+    }
+    memset(host, 0, hdr_bytes);  // the tile-queue counter starts at zero
+    memcpy(host + hdr_bytes, gd.data(), desc_bytes);
+    GTile *ht = (GTile *)(host + hdr_bytes + desc_bytes);
+    for (size_t i = 0; i < order.size(); ++i) ht[i] = tiles[order[i]];
+    if (hipMemcpyAsync(dev, host, total, hipMemcpyHostToDevice, s) != hipSuccess) {
+        if (!ws) (void)hipFreeAsync(dev, s);
         return MD_ERR_HIP;
     }
     const int ntiles = (int)tiles.size();
@@ -137,8 +162,25 @@ int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
     hipLaunchKernelGGL(md_grouped_kernel, dim3(grid), dim3(NT), 0, s, (const GDesc *)(dev + hdr_bytes),
                        (const GTile *)(dev + hdr_bytes + desc_bytes), ntiles, (int *)dev);
     const hipError_t le = hipGetLastError();
-    (void)hipFreeAsync(dev, s);
+    if (!ws) (void)hipFreeAsync(dev, s);
     return le == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+void grouped_ws_release(GroupedWs *ws) {
+    if (!ws) return;
+    if (ws->host) (void)hipHostFree(ws->host);
+    if (ws->dev) (void)hipFree(ws->dev);
+    ws->host = nullptr;
+    ws->dev = nullptr;
+    ws->cap = 0;
+}
+
+}  // namespace md
+
+extern "C" {
+
+int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
+    return md::grouped_enqueue(count, descs, nullptr, stream, nullptr);
 }
 
 // Tile-shape table file: one entry per line, "comp case bucket cfg" with comp

@@ -40,27 +40,29 @@ __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
         if (g.c_cplx) {
             if (g.c_dbl) {
                 double *c = (double *)g.C + 2 * off;
+                const double *cin = (const double *)g.Cin + 2 * off;
                 if (g.beta_zero) { c[0] = 0.0; c[1] = 0.0; }
                 else {
-                    const double br = g.beta_re, bi = g.beta_im, cr = c[0], ci = c[1];
+                    const double br = g.beta_re, bi = g.beta_im, cr = cin[0], ci = cin[1];
                     c[0] = fma(br, cr, -(bi * ci));
                     c[1] = fma(br, ci, bi * cr);
                 }
             } else {
                 float *c = (float *)g.C + 2 * off;
+                const float *cin = (const float *)g.Cin + 2 * off;
                 if (g.beta_zero) { c[0] = 0.0f; c[1] = 0.0f; }
                 else {
-                    const float br = (float)g.beta_re, bi = (float)g.beta_im, cr = c[0], ci = c[1];
+                    const float br = (float)g.beta_re, bi = (float)g.beta_im, cr = cin[0], ci = cin[1];
                     c[0] = fmaf(br, cr, -(bi * ci));
                     c[1] = fmaf(br, ci, bi * cr);
                 }
             }
         } else if (g.c_dbl) {
             double *c = (double *)g.C;
-            c[off] = g.beta_zero ? 0.0 : g.beta_re * c[off];
+            c[off] = g.beta_zero ? 0.0 : g.beta_re * ((const double *)g.Cin)[off];
         } else {
             float *c = (float *)g.C;
-            c[off] = g.beta_zero ? 0.0f : (float)g.beta_re * c[off];
+            c[off] = g.beta_zero ? 0.0f : (float)g.beta_re * ((const float *)g.Cin)[off];
         }
     }
 }

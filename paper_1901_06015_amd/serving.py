@@ -10,6 +10,11 @@ from . import _lib
 _DTN = {np.float32: "s", np.float64: "d", np.complex64: "c", np.complex128: "z"}
 
 
+class MdServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("slots", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("big_flops", ctypes.c_double), ("big_lanes", ctypes.c_int)]
+
+
 class MdRequest(ctypes.Structure):
     _fields_ = [("transa", ctypes.c_char), ("transb", ctypes.c_char),
                 ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
@@ -31,6 +36,7 @@ class MdServerStats(ctypes.Structure):
                 ("grouped_launches", ctypes.c_int64), ("plain_launches", ctypes.c_int64),
                 ("inflight_bytes", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64),
                 ("budget_bytes", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("pool_bytes", ctypes.c_int64), ("device_mallocs", ctypes.c_int64),
                 ("max_concurrent_batches", ctypes.c_int)]
 
 
@@ -39,7 +45,7 @@ def _bind():
     if getattr(L, "_md_server_bound", False):
         return L
     vp, i64, ci, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
-    L.md_server_create.argtypes = [i64, ci, ci, dbl, ctypes.POINTER(vp)]
+    L.md_server_create.argtypes = [ctypes.POINTER(MdServerConfig), ctypes.POINTER(vp)]
     L.md_server_destroy.argtypes = [vp]
     L.md_server_put.argtypes = [vp, vp, ci, i64, i64, ctypes.POINTER(i64)]
     L.md_server_drop.argtypes = [vp, i64]
@@ -64,10 +70,12 @@ class ServerError(RuntimeError):
 class Server:
     """Continuous-batching request loop over mdgemm on the current device."""
 
-    def __init__(self, budget_bytes, slots=4, max_batch=64, big_flops=2e9):
+    def __init__(self, budget_bytes, slots=4, max_batch=64, big_flops=2e9, big_lanes=1):
         self.L = _bind()
+        self.h = None
+        cfg = MdServerConfig(int(budget_bytes), slots, max_batch, float(big_flops), big_lanes)
         h = ctypes.c_void_p()
-        st = self.L.md_server_create(int(budget_bytes), slots, max_batch, float(big_flops), ctypes.byref(h))
+        st = self.L.md_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if st != 0:
             raise ServerError(st, "md_server_create")
         self.h = h

@@ -142,3 +142,15 @@ def test_server_create_without_device_fails_cleanly():
         assert e.status == _lib.MD_ERR_HIP
     else:
         raise AssertionError("server started without a device")
+
+
+def test_server_config_is_validated_before_any_device_call():
+    from paper_1901_06015_amd.serving import Server, ServerError
+    for kw in (dict(budget_bytes=0), dict(budget_bytes=1 << 30, slots=0), dict(budget_bytes=1 << 30, max_batch=0),
+               dict(budget_bytes=1 << 30, slots=2, big_lanes=3), dict(budget_bytes=1 << 30, big_lanes=0)):
+        try:
+            Server(**kw)
+        except ServerError as e:
+            assert e.status == _lib.MD_ERR_STATE, kw
+        else:
+            raise AssertionError("invalid configuration accepted: %r" % kw)
