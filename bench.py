@@ -568,7 +568,9 @@ def serving_workload(args):
     same server with batching and overlap off (one stream slot, every request
     its own mdgemm, in arrival order).  Reported: both forms' closed-loop
     capacity, the served form's latency at --load of its capacity, and both
-    forms' latency on one stream at --load of the plain form's capacity.
+    forms' latency on one stream at --load of the plain form's capacity, the
+    plain form on the headline trace, and a sample of requests re-run alone
+    (bitwise equal to their in-mix results).
     Latency = completion observed by the server minus submission."""
     import torch
     import oracle
@@ -625,18 +627,38 @@ def serving_workload(args):
     # the kept outputs against the oracle (elementwise bound)
     o = oracle.get()
     worst = 0.0
+    mixed_out = {}
     for i, h in outputs:
         t = pool.small[reqs[i][1]]
         tc, ta, tb, x = t["cabx"]
         m, n, k, sd = t["m"], t["n"], t["k"], t["seed"]
         A, B, C = inputs.matrix(m, k, ta, sd + 1), inputs.matrix(k, n, tb, sd + 2), inputs.matrix(m, n, tc, sd + 3)
         st, ref, g = o.gemm("N", "N", m, n, k, 1.0, A, ta, m, B, tb, k, 1.0, C, tc, m)
-        got = srv.fetch(h, m, n, tc).astype(np.complex128)
+        got_raw = srv.fetch(h, m, n, tc)
+        mixed_out[i] = got_raw
+        got = got_raw.astype(np.complex128)
         srv.drop(h)
         ux = 2.0 ** -24 if x == "s" else 2.0 ** -53
         uc = 2.0 ** -24 if tc in "sc" else 2.0 ** -53
         bound = 4 * k * ux * g + 4 * uc * np.abs(ref)
         worst = max(worst, float(np.max(np.abs(got - ref) / np.maximum(bound, 1e-300))))
+
+    # alone vs in the mix: each kept request again, by itself, bitwise
+    alone_equal = 0
+    for i, h in outputs:
+        t = pool.small[reqs[i][1]]
+        tk = pool.submit(srv, reqs[i], keep=True)
+        st, res = srv.wait(tk, 600)
+        a = srv.fetch(res.output, t["m"], t["n"], t["cabx"][0])
+        srv.drop(res.output)
+        srv.forget(tk)
+        alone_equal += int(np.array_equal(a, mixed_out[i]))
+
+    # the plain form on the same trace (it may be over capacity at this rate)
+    same_trace = None
+    if ppool is not None:
+        t_p, _, lag_p, _ = _open_loop(ppool, plain, reqs, arrivals, "plain@same")
+        same_trace = _latency_stats(t_p, is_big, flops)
 
     # both forms at one rate the plain form can sustain (--load of its capacity)
     equal = None
@@ -663,12 +685,13 @@ def serving_workload(args):
                        "big_fraction": round(float(is_big.mean()), 4), "slots": args.slots,
                        "max_batch": args.max_batch, "big_gflop": args.big_gflop, "big_lanes": args.big_lanes,
                        "tile_table": "autotuned" if tuned else "defaults", "budget_bytes": budget},
-            "latency": served, "equal_rate": equal,
+            "latency": served, "plain_same_trace": same_trace, "equal_rate": equal,
             "capacity": {"served": {"req_per_s": round(cap_rps, 1), "gflops": round(cap_gf, 1)}, "plain": pcap},
             "counters": {k: counters[k] for k in ("batches", "grouped_launches", "plain_launches",
                                                   "peak_inflight_bytes", "max_concurrent_batches",
                                                   "resident_bytes", "pool_bytes", "device_mallocs")},
-            "max_err_over_bound": worst, "checked_outputs": len(outputs)}
+            "max_err_over_bound": worst, "checked_outputs": len(outputs),
+            "alone_equals_in_mix": "%d of %d bitwise" % (alone_equal, len(outputs))}
     print(json.dumps(line), flush=True)
 
 
