@@ -161,8 +161,9 @@ def kernel_symbol(plan, transa="N", transb="N"):
     amnc = (transa == "N") if fast else True
     bmnc = (transb != "N") if fast else True
     b = lambda v: "true" if v else "false"
-    return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s>(md::GemmArgs)" % (
-        t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc))
+    cfg = "BigCfg" if plan["tile_m"] == 256 else "TileCfg"
+    return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s, md::%s<%s> >(md::GemmArgs)" % (
+        t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc), cfg, t)
 
 
 def traffic_record(symbol):

@@ -71,6 +71,18 @@ struct GemmArgs {
 
 enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
 
+// Tile configuration of the plain product kernel for (computation precision,
+// case, fast load path): 0 = 128 x 128 tiles (two workgroups per CU), 1 =
+// 256 x 128 tiles (one workgroup per CU).  The host's tile counts and the
+// device's kernel choice both come from here.  MD_BIG (bit 0: FP64, bit 1:
+// FP32) selects the large tiles at build time.
+#ifndef MD_BIG
+#define MD_BIG 0
+#endif
+constexpr int tile_kind(int prec, int cs, bool fast) {
+    return (!fast || prec == PREC_BF16X3) ? 0 : ((MD_BIG & (prec == PREC_D ? 1 : 2)) ? 1 : 0) + 0 * cs;
+}
+
 // Everything mdgemm decides before touching the device (mdgemm_api.cpp).
 struct Decision {
     int status = MD_OK;
@@ -87,7 +99,7 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
 // Host-side launchers (defined in mdgemm_kernels.hip).
 int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out);
 int launch_scale(const GemmArgs &a, void *stream);
-void tile_shape(int prec, int cs, int *bm, int *bn, int *bk);
+void tile_shape(int prec, int cs, bool fast, int *bm, int *bn, int *bk);
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len);
 
 // Out-of-place forms used by the serving loop of the same library:

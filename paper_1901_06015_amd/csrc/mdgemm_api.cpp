@@ -100,7 +100,7 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
 
     const Lowering L = lower_case(d.cs);
     int bm, bn, bk;
-    tile_shape(d.prec, d.cs, &bm, &bn, &bk);
+    tile_shape(d.prec, d.cs, g.a_vec && g.b_vec, &bm, &bn, &bk);
     const int64_t tmn_a = bm / (L.mdbl ? 2 : 1), tmn_b = bn / (L.ndbl ? 2 : 1);
     g.tiles_m = (int)((m + tmn_a - 1) / tmn_a);
     g.tiles_n = (int)((n + tmn_b - 1) / tmn_b);
@@ -164,7 +164,7 @@ int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     if (d.quick == 0) {
         out->flops = (double)L.flop_factor * (double)m * (double)n * (double)k;
         int bm, bn, bk;
-        tile_shape(d.prec, d.cs, &bm, &bn, &bk);
+        tile_shape(d.prec, d.cs, d.g.a_vec && d.g.b_vec, &bm, &bn, &bk);
         out->tile_m = bm; out->tile_n = bn; out->tile_k = bk;
         out->workgroups = (int64_t)d.g.tiles_m * d.g.tiles_n;
         kernel_name(d.prec, d.cs, d.g, out->kernel, (int)sizeof(out->kernel));

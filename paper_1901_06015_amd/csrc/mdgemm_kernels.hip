@@ -29,7 +29,11 @@ static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 #if MD_KT == 2
     hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
 #else
-    hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+    if constexpr (tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST) == 1)
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, BigCfg<KT>>), dim3(nwg), dim3(NT), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
 #endif
 }
 

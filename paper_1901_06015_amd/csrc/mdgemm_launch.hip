@@ -86,9 +86,8 @@ int launch_scale(const GemmArgs &a, void *stream) {
     return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
 }
 
-void tile_shape(int prec, int cs, int *bm, int *bn, int *bk) {
-    (void)cs;
-    *bm = 128;
+void tile_shape(int prec, int cs, bool fast, int *bm, int *bn, int *bk) {
+    *bm = tile_kind(prec, cs, fast) == 1 ? 256 : 128;
     *bn = 128;
     *bk = prec == PREC_D ? 16 : 32;
 }
