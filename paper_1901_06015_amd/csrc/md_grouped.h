@@ -7,7 +7,7 @@
 // an atomic counter until the table is exhausted.  Because one launch mixes
 // every variant, the tile routine decodes the domain case, the storage
 // precisions and the operand orientation at run time, element by element
-// (`fetch_elem`), instead of using the specialised staging of md_tile.h; the
+// (`GStager`), instead of using the specialised staging of md_tile.h; the
 // lowering it realises is the same (Figure "mixeddom" cases onto one real
 // product, Re/Im split in blocks of 16, 1e/1r arrangement for case 3), and the
 // epilogue is md_tile.h's.
@@ -33,17 +33,19 @@ struct GTile {
     int desc, tm, tn, pad;
 };
 
-// LDS bytes of each tile routine: two k-tiles ([k][mn], padded) of T, or
-// four bf16 planes for BF16x3; the kernel reserves the largest.
+// LDS bytes of each tile routine: two stages of the A' and B' k-tiles
+// ([k][mn], padded) of T, or two stages of four bf16 planes for BF16x3; the
+// kernel reserves the largest.
 template <class T, int WB>
 struct GShape {
     static constexpr int BM = 32 * WB;
     static constexpr int BK = (sizeof(T) == 8 ? 16 : 32) * 2 / WB;
     static constexpr int LDW = BM + (sizeof(T) == 8 ? 8 : 4);
-    static constexpr int SMEM = 2 * BK * LDW * (int)sizeof(T);
+    static constexpr int STAGE = 2 * BK * LDW;  // elements of T per stage (A' then B')
+    static constexpr int SMEM = 2 * STAGE * (int)sizeof(T);
 };
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int BF16X3_GROUPED_SMEM = 4 * 32 * (64 + 4) * 2;
+constexpr int BF16X3_GROUPED_SMEM = 2 * 4 * 32 * (64 + 4) * 2;
 constexpr int GROUPED_SMEM = cmax(cmax(cmax(GShape<float, 2>::SMEM, GShape<float, 4>::SMEM),
                                        cmax(GShape<double, 2>::SMEM, GShape<double, 4>::SMEM)),
                                   BF16X3_GROUPED_SMEM);
@@ -87,28 +89,44 @@ __device__ __forceinline__ GOp make_gop(const GemmArgs &g, int cs, bool is_a) {
 __device__ __forceinline__ bool gop_mn2(const GOp &o) { return o.mode == M_MNINT || o.mode == M_ONEE; }
 __device__ __forceinline__ bool gop_k2(const GOp &o) { return o.mode == M_KINT || o.mode == M_ONEE; }
 
-// Per-thread staging plan for E elements of a tile: for each element the
-// byte offset of its stored component at k-tile 0, whether it lies inside the
-// matrix along m/n, its k index inside the tile and its sign.  A k-tile t only
-// adds t*TK*kstride, so the loop carries no 64-bit index arithmetic.
-template <int E>
+// Per-thread staging plan for the E elements a thread moves per k-tile of a
+// BMN x BK tile.  For each element: the byte offset of its stored component
+// from the tile's origin at k-tile 0 (32-bit: the host keeps products whose
+// leading dimensions could overflow it out of the grouped launch), its k index
+// inside the tile, its sign and its LDS slot ([k][mn], row stride LDW).
+// Consecutive lanes take consecutive elements along the operand's contiguous
+// dimension in HBM (m/n for an m/n-contiguous operand, k otherwise), so every
+// load instruction reads whole cache lines.  Loads go through a buffer
+// resource that starts at the k-tile's origin and ends at the matrix's last
+// byte: an element outside the matrix gets an offset beyond the resource and
+// reads zero, with no branch and no 64-bit arithmetic in the loop.
+template <int E, int BMN, int BK, int LDW>
 struct GStager {
     const char *base;
-    int64_t off[E];
-    int kp[E];
-    bool mn_ok[E], neg[E];
-    int64_t kstride;  // bytes between consecutive stored k
+    int off[E], kp[E], slot[E];
+    uint32_t negm;   // bit e: element e enters negated
+    int64_t tile0;   // bytes from the matrix origin to the tile's origin at k-tile 0
+    int64_t kbytes;  // bytes between consecutive k-tiles
+    int64_t total;   // bytes from the matrix origin to its end
     int64_t K;
-    bool dbl;
-    __device__ __forceinline__ void init(const GOp &o, int64_t mn0, int BMN, int tid) {
+    int tk;
+    bool mnc;
+    __device__ __forceinline__ void init(const GOp &o, int64_t mn0, int tk_, int tid) {
         base = o.base;
-        dbl = o.dbl;
         K = o.K;
+        tk = tk_;
+        mnc = o.mnc;
         const int W = o.cplx ? 2 : 1, esz = o.dbl ? 8 : 4;
-        kstride = (o.mnc ? o.ld : 1) * W * esz;
+        const int64_t rows_st = o.mnc ? o.MN : o.K, cols_st = o.mnc ? o.K : o.MN;
+        total = ((cols_st - 1) * o.ld + rows_st) * W * esz;
+        tile0 = (o.mnc ? mn0 : mn0 * o.ld) * W * esz;
+        kbytes = (int64_t)tk * (o.mnc ? o.ld : 1) * W * esz;
+        negm = 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int idx = tid + e * NT, kr = idx / BMN, mr = idx % BMN;
+            const int idx = tid + e * NT;
+            const int kr = o.mnc ? idx / BMN : idx % BK, mr = o.mnc ? idx % BMN : idx / BK;
+            slot[e] = kr * LDW + mr;
             int i = mr, qm = 0;
             if (gop_mn2(o)) {
                 const int blk = mr >> 4;
@@ -132,20 +150,35 @@ struct GStager {
                 ng = (qm == 0 && qk == 1);
             }
             if (comp == 1 && o.conj) ng = !ng;
-            const int64_t mn = mn0 + i;
-            mn_ok[e] = mn < o.MN;
             kp[e] = p;
-            neg[e] = ng;
-            const int64_t elem = o.mnc ? (mn + (int64_t)p * o.ld) : ((int64_t)p + mn * o.ld);
-            off[e] = (elem * W + comp) * esz;
+            if (ng) negm |= 1u << e;
+            const int64_t rel = o.mnc ? ((int64_t)i + (int64_t)p * o.ld) : ((int64_t)p + (int64_t)i * o.ld);
+            off[e] = (mn0 + i < o.MN) ? (int)((rel * W + comp) * esz) : (int)0x80000000;
         }
     }
-    // Element e of the k-tile starting at stored k index k0 (zero outside).
-    __device__ __forceinline__ double get(int e, int64_t k0) const {
-        if (!mn_ok[e] || k0 + kp[e] >= K) return 0.0;
-        const char *p = base + off[e] + k0 * kstride;
-        const double v = dbl ? *(const double *)p : (double)*(const float *)p;
-        return neg[e] ? -v : v;
+    // Load the E elements of k-tile t, converted to T (float -> double is
+    // exact, double -> float rounds to nearest even) and signed.
+    template <class T, bool DBL>
+    __device__ __forceinline__ void load(int t, T (&r)[E]) const {
+        const int64_t b = tile0 + (int64_t)t * kbytes;
+        const int64_t rem = total - b;
+        const int nrec = rem > 0x7fffffffLL ? 0x7fffffff : (rem < 0 ? 0 : (int)rem);
+        __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)(base + b), (short)0, nrec, 0x00020000);
+        const int64_t kl = K - (int64_t)t * tk;
+        const int klim = kl > (1 << 30) ? (1 << 30) : (int)kl;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            // along k the resource's end only bounds an m/n-contiguous operand
+            const int o = (mnc || kp[e] < klim) ? off[e] : (int)0x80000000;
+            T v;
+            if constexpr (DBL) {
+                const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, o, 0, 0);
+                v = (T)__builtin_bit_cast(double, ((uint64_t)x[1] << 32) | x[0]);
+            } else {
+                v = (T)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0));
+            }
+            r[e] = ((negm >> e) & 1) ? -v : v;
+        }
     }
 };
 
@@ -194,7 +227,7 @@ __device__ __forceinline__ void grouped_epilogue(const GemmArgs &g, bool mdbl, b
 // FP64 MFMA.  WB: 16x16 blocks per wave and dimension (2: 64x64 workgroup
 // tile; 4: 128x128).  LDS holds one k-tile of A' and B' as [k][mn]; the next
 // k-tile's elements are prefetched into registers during the MFMAs.
-template <class T, int WB>
+template <class T, int WB, bool AD, bool BD>
 __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, char *smem) {
     typedef typename AccT<T>::type acc_t;
     // k depth per LDS tile: the 128x128 shape halves it so that every shape
@@ -204,8 +237,7 @@ __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, cha
     constexpr int BM = SH::BM, BN = SH::BM, BK = SH::BK, LDW = SH::LDW;
     static_assert(SH::SMEM <= GROUPED_SMEM, "grouped LDS too small");
     constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
-    T *la = (T *)smem;
-    T *lb = la + BK * LDW;
+    T *const buf = (T *)smem;  // stage s: A' at buf + s*STAGE, B' BK*LDW further
     const GemmArgs &g = d.g;
     const GOp oa = make_gop(g, d.cs, true), ob = make_gop(g, d.cs, false);
     const bool mdbl = gop_mn2(oa), ndbl = gop_mn2(ob), kdbl = gop_k2(oa);
@@ -222,34 +254,31 @@ __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, cha
 #pragma unroll
         for (int b = 0; b < WB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    GStager<EA> sa;
-    GStager<EB> sb;
-    sa.init(oa, mn0a, BM, tid);
-    sb.init(ob, mn0b, BN, tid);
-    T ra[EA], rb[EB];  // converted on load: float -> double is exact, double -> float rounds
+    GStager<EA, BM, BK, LDW> sa;
+    GStager<EB, BN, BK, LDW> sb;
+    sa.init(oa, mn0a, tk, tid);
+    sb.init(ob, mn0b, tk, tid);
+    T ra[EA], rb[EB];
     auto load = [&](int t) {
-#pragma unroll
-        for (int e = 0; e < EA; ++e) ra[e] = (T)sa.get(e, (int64_t)t * tk);
-#pragma unroll
-        for (int e = 0; e < EB; ++e) rb[e] = (T)sb.get(e, (int64_t)t * tk);
+        sa.template load<T, AD>(t, ra);
+        sb.template load<T, BD>(t, rb);
     };
-    auto store = [&]() {
+    auto store = [&](int stage) {
+        T *la = buf + stage * SH::STAGE, *lb = la + BK * LDW;
 #pragma unroll
-        for (int e = 0; e < EA; ++e) {
-            const int idx = tid + e * NT;
-            la[(idx / BM) * LDW + idx % BM] = ra[e];
-        }
+        for (int e = 0; e < EA; ++e) la[sa.slot[e]] = ra[e];
 #pragma unroll
-        for (int e = 0; e < EB; ++e) {
-            const int idx = tid + e * NT;
-            lb[(idx / BN) * LDW + idx % BN] = rb[e];
-        }
+        for (int e = 0; e < EB; ++e) lb[sb.slot[e]] = rb[e];
     };
 
+    // Two LDS stages: tile t+1 is loaded during the MFMAs of tile t and
+    // written to the other stage (last read before the previous barrier), so
+    // one barrier per k-tile suffices.
     load(0);
-    store();
+    store(0);
     __syncthreads();
     for (int t = 0; t < nk; ++t) {
+        const T *la = buf + (t & 1) * SH::STAGE, *lb = la + BK * LDW;
         if (t + 1 < nk) load(t + 1);
 #pragma unroll
         for (int s = 0; s < BK / 4; ++s) {
@@ -264,11 +293,8 @@ __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, cha
 #pragma unroll
                 for (int b = 0; b < WB; ++b) acc[a][b] = mfma16(fb[b], fa[a], acc[a][b]);
         }
+        if (t + 1 < nk) store((t + 1) & 1);
         __syncthreads();
-        if (t + 1 < nk) {
-            store();
-            __syncthreads();
-        }
     }
     grouped_epilogue<T, acc_t, WB>(g, mdbl, ndbl, ccplx, (int64_t)tm * tmn_a, (int64_t)tn * tmn_b, wm0, wn0,
                                    lane, acc);
@@ -276,16 +302,13 @@ __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, cha
 
 // BF16x3 form of grouped_tile: single-precision semantics from three bf16
 // products per 16x16x32 block (see md_tile_bf16.h).
-template <int WB>
+template <int WB, bool AD, bool BD>
 __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int tn, char *smem) {
     constexpr int BM = 32 * WB, BN = 32 * WB, BK = 32;
-    constexpr int LDW = BM + 4;
-    static_assert(4 * BK * LDW * 2 <= GROUPED_SMEM, "grouped LDS too small");
+    constexpr int LDW = BM + 4, PLANE = BK * LDW, STAGE = 4 * PLANE;
+    static_assert(2 * STAGE * 2 <= GROUPED_SMEM, "grouped LDS too small");
     constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
-    __bf16 *ah = (__bf16 *)smem;
-    __bf16 *al = ah + BK * LDW;
-    __bf16 *bh = al + BK * LDW;
-    __bf16 *bl = bh + BK * LDW;
+    __bf16 *const buf = (__bf16 *)smem;  // stage s: planes Ah, Al, Bh, Bl
     const GemmArgs &g = d.g;
     const GOp oa = make_gop(g, d.cs, true), ob = make_gop(g, d.cs, false);
     const bool mdbl = gop_mn2(oa), ndbl = gop_mn2(ob), kdbl = gop_k2(oa);
@@ -302,32 +325,25 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
 #pragma unroll
         for (int b = 0; b < WB; ++b) acc[a][b] = v4f{0, 0, 0, 0};
 
-    GStager<EA> sa;
-    GStager<EB> sb;
-    sa.init(oa, mn0a, BM, tid);
-    sb.init(ob, mn0b, BN, tid);
+    GStager<EA, BM, BK, LDW> sa;
+    GStager<EB, BN, BK, LDW> sb;
+    sa.init(oa, mn0a, tk, tid);
+    sb.init(ob, mn0b, tk, tid);
     float ra[EA], rb[EB];
     auto load = [&](int t) {
-#pragma unroll
-        for (int e = 0; e < EA; ++e) ra[e] = (float)sa.get(e, (int64_t)t * tk);
-#pragma unroll
-        for (int e = 0; e < EB; ++e) rb[e] = (float)sb.get(e, (int64_t)t * tk);
+        sa.template load<float, AD>(t, ra);
+        sb.template load<float, BD>(t, rb);
     };
     auto split = [](float v, __bf16 &h, __bf16 &l) {
         h = (__bf16)v;
         l = (__bf16)(v - (float)h);
     };
-    auto store = [&]() {
+    auto store = [&](int stage) {
+        __bf16 *ah = buf + stage * STAGE, *al = ah + PLANE, *bh = al + PLANE, *bl = bh + PLANE;
 #pragma unroll
-        for (int e = 0; e < EA; ++e) {
-            const int idx = tid + e * NT, o = (idx / BM) * LDW + idx % BM;
-            split(ra[e], ah[o], al[o]);
-        }
+        for (int e = 0; e < EA; ++e) split(ra[e], ah[sa.slot[e]], al[sa.slot[e]]);
 #pragma unroll
-        for (int e = 0; e < EB; ++e) {
-            const int idx = tid + e * NT, o = (idx / BN) * LDW + idx % BN;
-            split(rb[e], bh[o], bl[o]);
-        }
+        for (int e = 0; e < EB; ++e) split(rb[e], bh[sb.slot[e]], bl[sb.slot[e]]);
     };
     auto frag = [&](const __bf16 *plane, int w0, int i) {
         bf16x8 x;
@@ -338,9 +354,10 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
     };
 
     load(0);
-    store();
+    store(0);
     __syncthreads();
     for (int t = 0; t < nk; ++t) {
+        const __bf16 *ah = buf + (t & 1) * STAGE, *al = ah + PLANE, *bh = al + PLANE, *bl = bh + PLANE;
         if (t + 1 < nk) load(t + 1);
         bf16x8 fah[WB], fal[WB], fbh[WB], fbl[WB];
 #pragma unroll
@@ -358,11 +375,8 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
                 acc[a][b] = mfma_bf16(fbh[b], fal[a], acc[a][b]);
                 acc[a][b] = mfma_bf16(fbh[b], fah[a], acc[a][b]);
             }
+        if (t + 1 < nk) store((t + 1) & 1);
         __syncthreads();
-        if (t + 1 < nk) {
-            store();
-            __syncthreads();
-        }
     }
     grouped_epilogue<float, v4f, WB>(g, mdbl, ndbl, ccplx, (int64_t)tm * tmn_a, (int64_t)tn * tmn_b, wm0, wn0,
                                      lane, acc);
@@ -428,17 +442,33 @@ __global__ __launch_bounds__(NT, 2) void md_grouped_kernel(const GDesc *descs, c
             grouped_scale_tile(d.g, tm, tn);
             continue;
         }
-        const int sel = d.prec * GCFG_COUNT + d.cfg;
+        // one routine per (computation precision, tile shape, storage
+        // precisions of A and B); everything else is decoded per tile
+        const int sel = ((d.prec * GCFG_COUNT + d.cfg) * 2 + d.g.a_dbl) * 2 + d.g.b_dbl;
+#define MD_GSEL(p, c, ad, bd) ((((p) * GCFG_COUNT + (c)) * 2 + (ad)) * 2 + (bd))
+#define MD_GCASES(p, c, T, WB)                                                                              \
+    case MD_GSEL(p, c, 0, 0): grouped_tile<T, WB, false, false>(d, tm, tn, smem); break;                   \
+    case MD_GSEL(p, c, 0, 1): grouped_tile<T, WB, false, true>(d, tm, tn, smem); break;                    \
+    case MD_GSEL(p, c, 1, 0): grouped_tile<T, WB, true, false>(d, tm, tn, smem); break;                    \
+    case MD_GSEL(p, c, 1, 1): grouped_tile<T, WB, true, true>(d, tm, tn, smem); break;
+#define MD_GCASES_BF(c)                                                                                     \
+    case MD_GSEL(PREC_BF16X3, c, 0, 0): grouped_tile_bf16x3<2, false, false>(d, tm, tn, smem); break;      \
+    case MD_GSEL(PREC_BF16X3, c, 0, 1): grouped_tile_bf16x3<2, false, true>(d, tm, tn, smem); break;       \
+    case MD_GSEL(PREC_BF16X3, c, 1, 0): grouped_tile_bf16x3<2, true, false>(d, tm, tn, smem); break;       \
+    case MD_GSEL(PREC_BF16X3, c, 1, 1): grouped_tile_bf16x3<2, true, true>(d, tm, tn, smem); break;
         switch (sel) {
-        case PREC_S * GCFG_COUNT + GCFG_64: grouped_tile<float, 2>(d, tm, tn, smem); break;
-        case PREC_S * GCFG_COUNT + GCFG_128: grouped_tile<float, 4>(d, tm, tn, smem); break;
-        case PREC_D * GCFG_COUNT + GCFG_64: grouped_tile<double, 2>(d, tm, tn, smem); break;
-        case PREC_D * GCFG_COUNT + GCFG_128: grouped_tile<double, 4>(d, tm, tn, smem); break;
-        // BF16x3 has a single (64x64) shape in the grouped kernel
-        case PREC_BF16X3 * GCFG_COUNT + GCFG_64:
-        case PREC_BF16X3 * GCFG_COUNT + GCFG_128: grouped_tile_bf16x3<2>(d, tm, tn, smem); break;
+            MD_GCASES(PREC_S, GCFG_64, float, 2)
+            MD_GCASES(PREC_S, GCFG_128, float, 4)
+            MD_GCASES(PREC_D, GCFG_64, double, 2)
+            MD_GCASES(PREC_D, GCFG_128, double, 4)
+            // BF16x3 has a single (64x64) shape in the grouped kernel
+            MD_GCASES_BF(GCFG_64)
+            MD_GCASES_BF(GCFG_128)
         default: break;
         }
+#undef MD_GCASES_BF
+#undef MD_GCASES
+#undef MD_GSEL
     }
 }
 

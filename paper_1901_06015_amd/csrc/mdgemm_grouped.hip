@@ -68,6 +68,7 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
     std::vector<GDesc> gd;
     std::vector<GTile> tiles;
     std::vector<double> work;
+    std::vector<int64_t> alone;  // products run by the plain kernels instead
     gd.reserve(count);
     for (int64_t i = 0; i < count; ++i) {
         const md_gemm_desc &x = descs[i];
@@ -76,6 +77,12 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         if (d.status < 0) return -(int)(1000 * i + (-d.status));
         if (d.status != MD_OK) return d.status;
         if (d.quick == 1) continue;
+        // the grouped kernel addresses an operand tile with 32-bit offsets:
+        // 128 columns of 32 components of 16 bytes must span less than 2 GiB
+        if (d.quick == 0 && (x.lda >= ((int64_t)1 << 20) || x.ldb >= ((int64_t)1 << 20))) {
+            alone.push_back(i);
+            continue;
+        }
         GDesc e;
         memset(&e, 0, sizeof(e));
         e.g = d.g;
@@ -111,8 +118,15 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
                 work.push_back(w);
             }
     }
-    if (tiles.empty()) return MD_OK;
     if (tiles.size() > 0x7fffffffu) return MD_ERR_UNSUPPORTED;
+    auto run_alone = [&]() {
+        for (int64_t i : alone) {
+            const int rc = gemm_enqueue(descs[i], c_in ? c_in[i] : nullptr, stream);
+            if (rc != MD_OK) return rc;
+        }
+        return (int)MD_OK;
+    };
+    if (tiles.empty()) return run_alone();
     // Largest work first (LPT order) so the tail of the queue is short tiles.
     std::vector<int> order(tiles.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -163,7 +177,8 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
                        (const GTile *)(dev + hdr_bytes + desc_bytes), ntiles, (int *)dev);
     const hipError_t le = hipGetLastError();
     if (!ws) (void)hipFreeAsync(dev, s);
-    return le == hipSuccess ? MD_OK : MD_ERR_HIP;
+    if (le != hipSuccess) return MD_ERR_HIP;
+    return run_alone();
 }
 
 void grouped_ws_release(GroupedWs *ws) {
