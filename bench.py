@@ -153,15 +153,17 @@ def kernel_source_sha():
 
 
 def kernel_symbol(plan, transa="N", transb="N"):
-    """The demangled symbol rocprofv3 reports for the kernel a plan launches."""
-    name = plan["kernel"]
-    t = "double" if "_f64_" in name else "float"
-    fast = "_fast_" in name
-    ad, bd = name[-2] == "d", name[-1] == "d"
+    """The demangled symbol rocprofv3 reports for the kernel a plan launches
+    (plan kernel names read md_gemm_<prec>_case<c>_<path>_<A><B>_<tile>)."""
+    parts = plan["kernel"].split("_")
+    t = "double" if parts[2] == "f64" else "float"
+    fast = parts[4] == "fast"
+    ad, bd = parts[5][0] == "d", parts[5][1] == "d"
+    cfg = {"t128x128w4": "TileCfg", "t128x256w8": "WideN", "t256x128w8": "WideM",
+           "t128x128w8": "Deep"}[parts[6]]
     amnc = (transa == "N") if fast else True
     bmnc = (transb != "N") if fast else True
     b = lambda v: "true" if v else "false"
-    cfg = "BigCfg" if plan["tile_m"] == 256 else "TileCfg"
     return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s, md::%s<%s> >(md::GemmArgs)" % (
         t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc), cfg, t)
 

@@ -72,15 +72,21 @@ struct GemmArgs {
 enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
 
 // Tile configuration of the plain product kernel for (computation precision,
-// case, fast load path): 0 = 128 x 128 tiles (two workgroups per CU), 1 =
-// 256 x 128 tiles (one workgroup per CU).  The host's tile counts and the
-// device's kernel choice both come from here.  MD_BIG (bit 0: FP64, bit 1:
-// FP32) selects the large tiles at build time.
-#ifndef MD_BIG
-#define MD_BIG 0
+// case, fast load path): 0 = 128 x 128 tiles of 4 waves, 1 = 128 x 256 and
+// 2 = 256 x 128 tiles of 8 waves, 3 = 128 x 128 tiles of 8 waves.  The host's
+// tile counts and the device's kernel choice both come from here.  MD_WIDE
+// selects them at build time: bits 0/1 FP64/FP32 -> 128 x 256, bits 2/3 ->
+// 256 x 128, bits 4/5 -> 8-wave 128 x 128.  Default: 8-wave 128 x 128 for
+// FP32 (measured at m=n=k=4096: 1.00-1.11x the 4-wave tile, 1.047x on
+// average), 4 waves for FP64 (the 8-wave tile measured 0.98-1.03x).
+#ifndef MD_WIDE
+#define MD_WIDE 32
 #endif
 constexpr int tile_kind(int prec, int cs, bool fast) {
-    return (!fast || prec == PREC_BF16X3) ? 0 : ((MD_BIG & (prec == PREC_D ? 1 : 2)) ? 1 : 0) + 0 * cs;
+    return (!fast || prec == PREC_BF16X3) ? 0
+         : (MD_WIDE & (prec == PREC_D ? 1 : 2)) ? 1
+         : (MD_WIDE & (prec == PREC_D ? 4 : 8)) ? 2
+         : (MD_WIDE & (prec == PREC_D ? 16 : 32)) ? 3 : 0 * cs;
 }
 
 // Everything mdgemm decides before touching the device (mdgemm_api.cpp).

@@ -58,25 +58,35 @@ template <> struct Pad<double> { static constexpr int PADW = 8, PADK = 2; };
 template <> struct Pad<float> { static constexpr int PADW = 4, PADK = 4; };
 
 // Tile configuration: workgroup tile BM x BN of the real product, computed by
-// 2 x 2 waves of (BM/2) x (BN/2) = WMB x WNB MFMA blocks; k depth BK of one
-// LDS tile; OCC waves per SIMD (the register budget: 512 / OCC per lane).
-template <class T, int BM_, int BN_, int BK_, int OCC_>
+// WGM x WGN waves of (BM/WGM) x (BN/WGN) = WMB x WNB MFMA blocks; k depth BK
+// of one LDS tile; OCC waves per SIMD the kernel is compiled for (the
+// register budget: 512 / OCC per lane).
+template <class T, int BM_, int BN_, int BK_, int OCC_, int WGM_ = 2, int WGN_ = 2>
 struct TCfg {
-    static constexpr int BM = BM_, BN = BN_, BK = BK_, OCC = OCC_;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, OCC = OCC_, WGM = WGM_, WGN = WGN_;
+    static constexpr int NT = 64 * WGM * WGN;  // threads per workgroup
     static constexpr int PADW = Pad<T>::PADW, PADK = Pad<T>::PADK;
-    static constexpr int WMB = BM / (2 * 16), WNB = BN / (2 * 16);
+    static constexpr int WMB = BM / (WGM * 16), WNB = BN / (WGN * 16);
 };
-// The default configuration (also the BF16x3 kernel's): 128 x 128 tiles, two
-// workgroups per CU.
+// The default configuration (also the BF16x3 kernel's): 128 x 128 tiles of
+// 4 waves, two workgroups per CU.
 template <class T> struct TileCfg;
 template <> struct TileCfg<double> : TCfg<double, 128, 128, 16, MD_OCC> {};
 template <> struct TileCfg<float> : TCfg<float, 128, 128, 32, MD_OCC> {};
-// The large configuration: 256 x 128 tiles, one workgroup per CU, each wave
-// 128 x 64 -- half the operand traffic per flop along n and twice the MFMAs
-// per fragment read.
-template <class T> struct BigCfg;
-template <> struct BigCfg<double> : TCfg<double, 256, 128, 16, 1> {};
-template <> struct BigCfg<float> : TCfg<float, 256, 128, 32, 1> {};
+// Wide configurations: 8 waves of 64 x 64 (the default's wave tile and
+// register budget, two waves per SIMD) on one 128 x 256 (WideN) or 256 x 128
+// (WideM) tile per CU, so a CU stages a quarter fewer operand bytes per k.
+template <class T> struct WideN;
+template <> struct WideN<double> : TCfg<double, 128, 256, 16, 2, 2, 4> {};
+template <> struct WideN<float> : TCfg<float, 128, 256, 32, 2, 2, 4> {};
+template <class T> struct WideM;
+template <> struct WideM<double> : TCfg<double, 256, 128, 16, 2, 4, 2> {};
+template <> struct WideM<float> : TCfg<float, 256, 128, 32, 2, 4, 2> {};
+// Deep configuration: the default 128 x 128 tile split over 8 waves of
+// 64 x 32, four waves per SIMD (128 registers per lane).
+template <class T> struct Deep;
+template <> struct Deep<double> : TCfg<double, 128, 128, 16, 4, 2, 4> {};
+template <> struct Deep<float> : TCfg<float, 128, 128, 32, 4, 2, 4> {};
 
 template <class T> struct AccT;
 template <> struct AccT<double> { typedef v4d type; };
@@ -150,15 +160,18 @@ struct Stage {
     static constexpr int ESZ = SDBL ? 8 : 4;          // bytes per stored component
     static constexpr int CW = 16 / ESZ;               // components per chunk (one 16-byte load)
     static constexpr int CHUNKS = TMN * TK * W / CW;
-    static constexpr int PER = CHUNKS / NT;
+    // A tile with fewer chunks than threads (possible with 8 waves) leaves
+    // the last threads idle; chunk counts are multiples of 64, so whole waves.
+    static constexpr bool PARTIAL = CHUNKS < C::NT;
+    static constexpr int PER = PARTIAL ? 1 : CHUNKS / C::NT;
     static constexpr int CPC_MN = TMN * W / CW, CPC_K = TK * W / CW;
     // Sign applied to Im when it is placed at an odd k' row: -Im(A) in case 2ab
     // realises Re(AB) = ArBr - AiBi; B's Im enters positively.
     static constexpr bool KNEG = IS_A;
     static_assert(FAST || MNC, "the generic path stages into the [k][mn] layout");
-    static_assert(CHUNKS % NT == 0, "tile does not split evenly over the workgroup");
+    static_assert(PARTIAL ? CHUNKS % 64 == 0 : CHUNKS % C::NT == 0, "tile does not split evenly over the workgroup");
     static_assert((TMN * W) % CW == 0 && (TK * W) % CW == 0, "chunks straddle columns");
-    static_assert((CPC_MN & (CPC_MN - 1)) == 0 && (CPC_K & (CPC_K - 1)) == 0 && CPC_MN <= NT && CPC_K <= NT,
+    static_assert((CPC_MN & (CPC_MN - 1)) == 0 && (CPC_K & (CPC_K - 1)) == 0 && CPC_MN <= C::NT && CPC_K <= C::NT,
                   "chunk grid must be a power of two no wider than the workgroup");
 
     uint4 raw[PER];  // one tile's loads, held until converted
@@ -170,6 +183,7 @@ struct Stage {
     int cpc_log;          // log2 of chunks per stored column inside a tile
     int pos, col0;        // this thread's chunk 0: position in its column, column in the tile
     int col_step;         // columns between a thread's consecutive chunks
+    bool active;          // this thread stages a chunk (always, unless PARTIAL)
 
     __device__ __forceinline__ Stage(const GemmArgs &g, int tid, int64_t mn0_) {
         const int tr = IS_A ? g.ta : g.tb;
@@ -184,7 +198,8 @@ struct Stage {
         cpc_log = __builtin_ctz(cpc);
         pos = tid & (cpc - 1);
         col0 = tid >> cpc_log;
-        col_step = NT >> cpc_log;
+        col_step = C::NT >> cpc_log;
+        active = !PARTIAL || tid < CHUNKS;
         const int64_t rows_st = mn_contig ? MN : K, cols_st = mn_contig ? K : MN;
         total_bytes = ((cols_st - 1) * ld + rows_st) * W * ESZ;
     }
@@ -209,7 +224,7 @@ struct Stage {
             const int col = col0 + c * col_step;
             const int e_mn = MNC ? epos : col;
             const int e_k = MNC ? col : epos;
-            const bool ok = (e_mn < mlim) && (e_k < klim);
+            const bool ok = (!PARTIAL || active) && (e_mn < mlim) && (e_k < klim);
             const uint32_t off = ok ? (uint32_t)col * col_bytes + (uint32_t)(pos * 16) : 0x80000000u;
             const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
             raw[c] = make_uint4(x[0], x[1], x[2], x[3]);
@@ -225,7 +240,7 @@ struct Stage {
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int64_t col = c0 + col0 + c * col_step, comp0 = r0 * W + pos * CW;
-            const bool colok = col < cols_st;
+            const bool colok = (!PARTIAL || active) && col < cols_st;
             const int64_t idx = col * col_stride + comp0;
             if constexpr (SDBL) {
                 const uint2 *p = (const uint2 *)base + idx;
@@ -300,6 +315,7 @@ struct Stage {
     // Convert the staged registers and hand every element to `out`.
     template <class Out>
     __device__ __forceinline__ void store_to(Out out) const {
+        if (PARTIAL && !active) return;
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;
@@ -473,7 +489,7 @@ struct Frag {
 #endif
 
 template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<T>>
-__global__ __launch_bounds__(NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
     typedef Stage<T, CS, true, FAST, AD, AMNC, C> SA;
     typedef Stage<T, CS, false, FAST, BD, BMNC, C> SB;
     constexpr bool PIPE = sizeof(T) == 4 ? MD_PIPE_F32 : MD_PIPE_F64;
@@ -487,7 +503,7 @@ __global__ __launch_bounds__(NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) T sB[2][SB::L::SIZE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave & 1) * (C::BM / 2), wn0 = (wave >> 1) * (C::BN / 2);
+    const int wm0 = (wave % C::WGM) * (C::BM / C::WGM), wn0 = (wave / C::WGM) * (C::BN / C::WGN);
     int tm, tn;
     map_tile(blockIdx.x, gridDim.x, g.tiles_m, g.tiles_n, &tm, &tn);
     const int64_t mn0a = (int64_t)tm * SA::TMN, mn0b = (int64_t)tn * SB::TMN;

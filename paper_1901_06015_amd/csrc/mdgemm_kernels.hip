@@ -29,9 +29,16 @@ static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 #if MD_KT == 2
     hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
 #else
-    if constexpr (tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST) == 1)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, BigCfg<KT>>), dim3(nwg), dim3(NT), 0,
-                           s, a);
+    constexpr int kind = tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST);
+    if constexpr (kind == 1)
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideN<KT>>), dim3(nwg),
+                           dim3(WideN<KT>::NT), 0, s, a);
+    else if constexpr (kind == 2)
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideM<KT>>), dim3(nwg),
+                           dim3(WideM<KT>::NT), 0, s, a);
+    else if constexpr (kind == 3)
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, Deep<KT>>), dim3(nwg),
+                           dim3(Deep<KT>::NT), 0, s, a);
     else
         hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
 #endif
