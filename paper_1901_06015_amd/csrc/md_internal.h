@@ -77,10 +77,10 @@ enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
 // tile counts and the device's kernel choice both come from here.  MD_WIDE
 // selects them at build time: bits 0/1 FP64/FP32 -> 128 x 256, bits 2/3 ->
 // 256 x 128, bits 4/5 -> 8-wave 128 x 128.  Default: 8-wave 128 x 128 for
-// FP32 (measured at m=n=k=4096: 1.00-1.11x the 4-wave tile, 1.047x on
-// average), 4 waves for FP64 (the 8-wave tile measured 0.98-1.03x).
+// both (measured at m=n=k=4096 against the 4-wave tile: FP32 1.00-1.11x,
+// 1.047x on average; FP64 0.99-1.05x, 1.028x on average).
 #ifndef MD_WIDE
-#define MD_WIDE 32
+#define MD_WIDE 48
 #endif
 constexpr int tile_kind(int prec, int cs, bool fast) {
     return (!fast || prec == PREC_BF16X3) ? 0

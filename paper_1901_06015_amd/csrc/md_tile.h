@@ -60,10 +60,12 @@ template <> struct Pad<float> { static constexpr int PADW = 4, PADK = 4; };
 // Tile configuration: workgroup tile BM x BN of the real product, computed by
 // WGM x WGN waves of (BM/WGM) x (BN/WGN) = WMB x WNB MFMA blocks; k depth BK
 // of one LDS tile; OCC waves per SIMD the kernel is compiled for (the
-// register budget: 512 / OCC per lane).
-template <class T, int BM_, int BN_, int BK_, int OCC_, int WGM_ = 2, int WGN_ = 2>
+// register budget: 512 / OCC per lane); PIPE the order of the k loop
+// (md_gemm_kernel).
+template <class T, int BM_, int BN_, int BK_, int OCC_, int WGM_ = 2, int WGN_ = 2, bool PIPE_ = true>
 struct TCfg {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, OCC = OCC_, WGM = WGM_, WGN = WGN_;
+    static constexpr bool PIPE = PIPE_;
     static constexpr int NT = 64 * WGM * WGN;  // threads per workgroup
     static constexpr int PADW = Pad<T>::PADW, PADK = Pad<T>::PADK;
     static constexpr int WMB = BM / (WGM * 16), WNB = BN / (WGN * 16);
@@ -71,7 +73,7 @@ struct TCfg {
 // The default configuration (also the BF16x3 kernel's): 128 x 128 tiles of
 // 4 waves, two workgroups per CU.
 template <class T> struct TileCfg;
-template <> struct TileCfg<double> : TCfg<double, 128, 128, 16, MD_OCC> {};
+template <> struct TileCfg<double> : TCfg<double, 128, 128, 16, MD_OCC, 2, 2, false> {};
 template <> struct TileCfg<float> : TCfg<float, 128, 128, 32, MD_OCC> {};
 // Wide configurations: 8 waves of 64 x 64 (the default's wave tile and
 // register budget, two waves per SIMD) on one 128 x 256 (WideN) or 256 x 128
@@ -474,25 +476,19 @@ struct Frag {
     }
 };
 
-// Order of the k loop.  Early store (MD_PIPE_F32 / MD_PIPE_F64 = 1): each
-// iteration first writes the staged registers (tile t+1) to the free LDS
-// buffer and at once issues the global loads of tile t+2, so a load has a
-// whole iteration of MFMAs to arrive.  Late store (0): the staged tile is
-// written during the last k-step and the next loads follow the barrier.
-// Measured at m=n=k=4096: early store is up to 8 % faster for FP32, late
-// store up to 5 % faster for FP64.
-#ifndef MD_PIPE_F32
-#define MD_PIPE_F32 1
-#endif
-#ifndef MD_PIPE_F64
-#define MD_PIPE_F64 0
-#endif
+// Order of the k loop (C::PIPE).  Early store: each iteration first writes
+// the staged registers (tile t+1) to the free LDS buffer and at once issues
+// the global loads of tile t+2, so a load has a whole iteration of MFMAs to
+// arrive.  Late store: the staged tile is written during the last k-step and
+// the next loads follow the barrier.  Measured at m=n=k=4096: early store is
+// faster for every configuration except FP64 on 4 waves (late store up to 5 %
+// faster there).
 
 template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<T>>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
     typedef Stage<T, CS, true, FAST, AD, AMNC, C> SA;
     typedef Stage<T, CS, false, FAST, BD, BMNC, C> SB;
-    constexpr bool PIPE = sizeof(T) == 4 ? MD_PIPE_F32 : MD_PIPE_F64;
+    constexpr bool PIPE = C::PIPE;
     constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef typename AccT<T>::type acc_t;
     static_assert(SA::TK == SB::TK, "A and B disagree on the k lowering");
