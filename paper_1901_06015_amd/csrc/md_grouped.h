@@ -92,8 +92,9 @@ __device__ __forceinline__ bool gop_k2(const GOp &o) { return o.mode == M_KINT |
 // Per-thread staging plan for the E elements a thread moves per k-tile of a
 // BMN x BK tile.  For each element: the byte offset of its stored component
 // from the tile's origin at k-tile 0 (32-bit: the host keeps products whose
-// leading dimensions could overflow it out of the grouped launch), its k index
-// inside the tile, its sign and its LDS slot ([k][mn], row stride LDW).
+// leading dimensions could overflow it out of the grouped launch) and its
+// sign; its k index inside the tile and its LDS slot ([k][mn], row stride
+// LDW) follow from the thread index and are recomputed where needed.
 // Consecutive lanes take consecutive elements along the operand's contiguous
 // dimension in HBM (m/n for an m/n-contiguous operand, k otherwise), so every
 // load instruction reads whole cache lines.  Loads go through a buffer
@@ -103,19 +104,31 @@ __device__ __forceinline__ bool gop_k2(const GOp &o) { return o.mode == M_KINT |
 template <int E, int BMN, int BK, int LDW>
 struct GStager {
     const char *base;
-    int off[E], kp[E], slot[E];
+    int off[E];
     uint32_t negm;   // bit e: element e enters negated
     int64_t tile0;   // bytes from the matrix origin to the tile's origin at k-tile 0
     int64_t kbytes;  // bytes between consecutive k-tiles
     int64_t total;   // bytes from the matrix origin to its end
     int64_t K;
     int tk;
-    bool mnc;
+    bool mnc, k2;
+    // tile coordinates (k row, m/n column) of element e of this thread
+    __device__ __forceinline__ int kr_of(int e) const {
+        const int idx = (int)threadIdx.x + e * NT;
+        return mnc ? idx / BMN : idx % BK;
+    }
+    __device__ __forceinline__ int mr_of(int e) const {
+        const int idx = (int)threadIdx.x + e * NT;
+        return mnc ? idx % BMN : idx / BK;
+    }
+    __device__ __forceinline__ int slot(int e) const { return kr_of(e) * LDW + mr_of(e); }
+    __device__ __forceinline__ int kp(int e) const { return k2 ? kr_of(e) >> 1 : kr_of(e); }
     __device__ __forceinline__ void init(const GOp &o, int64_t mn0, int tk_, int tid) {
         base = o.base;
         K = o.K;
         tk = tk_;
         mnc = o.mnc;
+        k2 = gop_k2(o);
         const int W = o.cplx ? 2 : 1, esz = o.dbl ? 8 : 4;
         const int64_t rows_st = o.mnc ? o.MN : o.K, cols_st = o.mnc ? o.K : o.MN;
         total = ((cols_st - 1) * o.ld + rows_st) * W * esz;
@@ -126,7 +139,6 @@ struct GStager {
         for (int e = 0; e < E; ++e) {
             const int idx = tid + e * NT;
             const int kr = o.mnc ? idx / BMN : idx % BK, mr = o.mnc ? idx % BMN : idx / BK;
-            slot[e] = kr * LDW + mr;
             int i = mr, qm = 0;
             if (gop_mn2(o)) {
                 const int blk = mr >> 4;
@@ -150,7 +162,6 @@ struct GStager {
                 ng = (qm == 0 && qk == 1);
             }
             if (comp == 1 && o.conj) ng = !ng;
-            kp[e] = p;
             if (ng) negm |= 1u << e;
             const int64_t rel = o.mnc ? ((int64_t)i + (int64_t)p * o.ld) : ((int64_t)p + (int64_t)i * o.ld);
             off[e] = (mn0 + i < o.MN) ? (int)((rel * W + comp) * esz) : (int)0x80000000;
@@ -169,7 +180,7 @@ struct GStager {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             // along k the resource's end only bounds an m/n-contiguous operand
-            const int o = (mnc || kp[e] < klim) ? off[e] : (int)0x80000000;
+            const int o = (mnc || kp(e) < klim) ? off[e] : (int)0x80000000;
             T v;
             if constexpr (DBL) {
                 const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, o, 0, 0);
@@ -266,9 +277,9 @@ __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, cha
     auto store = [&](int stage) {
         T *la = buf + stage * SH::STAGE, *lb = la + BK * LDW;
 #pragma unroll
-        for (int e = 0; e < EA; ++e) la[sa.slot[e]] = ra[e];
+        for (int e = 0; e < EA; ++e) la[sa.slot(e)] = ra[e];
 #pragma unroll
-        for (int e = 0; e < EB; ++e) lb[sb.slot[e]] = rb[e];
+        for (int e = 0; e < EB; ++e) lb[sb.slot(e)] = rb[e];
     };
 
     // Two LDS stages: tile t+1 is loaded during the MFMAs of tile t and
@@ -341,9 +352,9 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
     auto store = [&](int stage) {
         __bf16 *ah = buf + stage * STAGE, *al = ah + PLANE, *bh = al + PLANE, *bl = bh + PLANE;
 #pragma unroll
-        for (int e = 0; e < EA; ++e) split(ra[e], ah[sa.slot[e]], al[sa.slot[e]]);
+        for (int e = 0; e < EA; ++e) split(ra[e], ah[sa.slot(e)], al[sa.slot(e)]);
 #pragma unroll
-        for (int e = 0; e < EB; ++e) split(rb[e], bh[sb.slot[e]], bl[sb.slot[e]]);
+        for (int e = 0; e < EB; ++e) split(rb[e], bh[sb.slot(e)], bl[sb.slot(e)]);
     };
     auto frag = [&](const __bf16 *plane, int w0, int i) {
         bf16x8 x;
@@ -420,10 +431,17 @@ __device__ __forceinline__ void grouped_scale_tile(const GemmArgs &g, int tm, in
 
 
 
+// Workgroups of the persistent kernel per CU (its register budget is
+// 512 / GROUPED_OCC per lane; the grid is GROUPED_OCC x the CU count).
+#ifndef MD_GOCC
+#define MD_GOCC 2
+#endif
+constexpr int GROUPED_OCC = MD_GOCC;
+
 // The persistent kernel.  `hdr[0]` is the tile counter (zeroed by the host's
 // upload of the table); every workgroup exits once the counter passes
 // `ntiles`.
-__global__ __launch_bounds__(NT, 2) void md_grouped_kernel(const GDesc *descs, const GTile *tiles, int ntiles,
+__global__ __launch_bounds__(NT, GROUPED_OCC) void md_grouped_kernel(const GDesc *descs, const GTile *tiles, int ntiles,
                                                             int *hdr) {
     __shared__ __attribute__((aligned(16))) char smem[GROUPED_SMEM];
     __shared__ int s_t;
@@ -460,7 +478,9 @@ __global__ __launch_bounds__(NT, 2) void md_grouped_kernel(const GDesc *descs, c
             MD_GCASES(PREC_S, GCFG_64, float, 2)
             MD_GCASES(PREC_S, GCFG_128, float, 4)
             MD_GCASES(PREC_D, GCFG_64, double, 2)
+#if MD_GOCC < 3
             MD_GCASES(PREC_D, GCFG_128, double, 4)
+#endif
             // BF16x3 has a single (64x64) shape in the grouped kernel
             MD_GCASES_BF(GCFG_64)
             MD_GCASES_BF(GCFG_128)

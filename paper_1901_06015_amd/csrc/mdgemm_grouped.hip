@@ -36,6 +36,7 @@ int bucket_of(int64_t dim) {
 
 int choose_cfg(int prec, int cs, int64_t m_real, int64_t n_real) {
     if (prec == PREC_BF16X3) return GCFG_64;  // the only BF16x3 shape of the grouped kernel
+    if (GROUPED_OCC >= 3 && prec == PREC_D) return GCFG_64;  // no FP64 128 shape at this occupancy
     std::lock_guard<std::mutex> lk(g_table_mu);
     if (!g_table_init) default_table();
     return g_table[prec][cs][bucket_of(std::max(m_real, n_real))];
@@ -172,7 +173,7 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         return MD_ERR_HIP;
     }
     const int ntiles = (int)tiles.size();
-    const int grid = std::min(ntiles, num_cu() * 2);
+    const int grid = std::min(ntiles, num_cu() * GROUPED_OCC);
     hipLaunchKernelGGL(md_grouped_kernel, dim3(grid), dim3(NT), 0, s, (const GDesc *)(dev + hdr_bytes),
                        (const GTile *)(dev + hdr_bytes + desc_bytes), ntiles, (int *)dev);
     const hipError_t le = hipGetLastError();

@@ -151,3 +151,31 @@ def test_grouped_invalid_descriptor_enqueues_nothing():
     assert st == -(1000 * 2 + 1)
     for a, b in zip(before, keep[1::2]):
         assert torch.equal(a, b)
+
+
+def test_grouped_huge_leading_dimension_runs_alongside():
+    """A product whose leading dimension is too large for the grouped kernel's
+    32-bit tile offsets (lda >= 2^20) runs on the plain kernels in the same
+    call; it and the products around it still match the oracle."""
+    entries = make_entries(6, seed=13, lo=8, hi=96, comps=("s", "d"))
+    entries[2]["k"], entries[2]["transa"] = 8, "N"  # A is m x 8 inside a 2^20-row buffer
+    say("grouped with one huge-lda product")
+    o = oracle.get()
+    descs, keep = [], []
+    for idx, e in enumerate(entries):
+        ar, ac = (e["m"], e["k"]) if e["transa"] == "N" else (e["k"], e["m"])
+        br, bc = (e["k"], e["n"]) if e["transb"] == "N" else (e["n"], e["k"])
+        lda = (1 << 20) + 8 if idx == 2 else ar
+        A = inputs.matrix(ar, ac, e["ta"], e["seed"] * 3 + 1, ld=lda)
+        B = inputs.matrix(br, bc, e["tb"], e["seed"] * 3 + 2)
+        C = inputs.matrix(e["m"], e["n"], e["tc"], e["seed"] * 3 + 3, ld=max(1, e["m"]) + 2, pad=gu.SENTINEL)
+        dA, dB, dC = gu.to_device(A), gu.to_device(B), gu.to_device(C)
+        descs.append(_lib.make_desc(e["transa"], e["transb"], e["m"], e["n"], e["k"], e["alpha"],
+                                    dA.data_ptr(), e["ta"], A.shape[0], dB.data_ptr(), e["tb"], B.shape[0],
+                                    e["beta"], dC.data_ptr(), e["tc"], C.shape[0], e["comp"]))
+        keep.append((A, B, C, dA, dB, dC))
+    st = _lib.mdgemm_grouped(descs, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert keep[2][0].shape[0] >= 1 << 20
+    check_all(entries, keep)
