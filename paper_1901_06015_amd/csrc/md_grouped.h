@@ -356,12 +356,14 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
 #pragma unroll
         for (int e = 0; e < EB; ++e) split(rb[e], bh[sb.slot(e)], bl[sb.slot(e)]);
     };
+    static_assert(LDW % 4 == 0, "transposing reads need 8-byte aligned rows");
+    // k = 8g .. 8g+7 of column w0 + 16 i + (lane & 15) in two transposing
+    // reads (see read_bf16_frag)
     auto frag = [&](const __bf16 *plane, int w0, int i) {
-        bf16x8 x;
-        const int gq = lane >> 4, mm = w0 + 16 * i + (lane & 15);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = plane[(8 * gq + j) * LDW + mm];
-        return x;
+        const int gq = lane >> 4, a4 = lane & 3, j4 = (lane >> 2) & 3;
+        const __bf16 *p = plane + (8 * gq + j4) * LDW + w0 + 16 * i + 4 * a4;
+        const bf16x4 x0 = lds_read_tr16(p), x1 = lds_read_tr16(p + 4 * LDW);
+        return bf16x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
     };
 
     load(0);

@@ -43,18 +43,36 @@ struct SplitOut {
     }
 };
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+typedef __attribute__((address_space(3))) __bf16 lds_bf16;
+
+// Transposing LDS read (ds_read_b64_tr_b16): inside each group of 16 lanes,
+// lane 4a+b receives element b of the 8-byte reads addressed by lanes a,
+// a+4, a+8 and a+12 (measured on gfx950).
+__device__ __forceinline__ bf16x4 lds_read_tr16(const __bf16 *p) {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4 *)(lds_bf16 *)p);
+}
+
 // Fragment of one 16x16x32 MFMA operand for block i: lane group g = lane >> 4
-// holds k = 8g .. 8g+7 of row (or column) w0 + 16 i + (lane & 15).
+// holds k = 8g .. 8g+7 of row (or column) w0 + 16 i + (lane & 15).  From a
+// [k][mn] plane it takes two transposing reads: lane 16g + a + 4j addresses
+// k = 8g + j (then 8g + j + 4) at columns 4a .. 4a+3 of the block, so lane
+// 16g + r receives the 4 consecutive k of column r; from a [mn][k] plane the
+// 8 k are one 16-byte read.
 template <bool MNC, int BMN>
 __device__ __forceinline__ bf16x8 read_bf16_frag(const __bf16 *plane, int lane, int w0, int i) {
     typedef LayBF<MNC, BMN> L;
-    const int g = lane >> 4, mm = w0 + 16 * i + (lane & 15);
+    static_assert(!MNC || L::LD % 4 == 0, "transposing reads need 8-byte aligned rows");
+    const int g = lane >> 4;
     if constexpr (MNC) {
-        bf16x8 x;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = plane[L::at(8 * g + j, mm)];
-        return x;
+        const int a4 = lane & 3, j4 = (lane >> 2) & 3;
+        const int row = 8 * g + j4, col = w0 + 16 * i + 4 * a4;
+        const bf16x4 x0 = lds_read_tr16(&plane[L::at(row, col)]);
+        const bf16x4 x1 = lds_read_tr16(&plane[L::at(row + 4, col)]);
+        return bf16x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
     } else {
+        const int mm = w0 + 16 * i + (lane & 15);
         return *(const bf16x8 *)&plane[L::at(8 * g, mm)];
     }
 }
@@ -63,12 +81,12 @@ __device__ __forceinline__ v4f mfma_bf16(bf16x8 x, bf16x8 y, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
 }
 
-template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC>
-__global__ __launch_bounds__(NT, 2) void md_bf16x3_kernel(GemmArgs g) {
-    typedef TileCfg<float> C;
+template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<float>>
+__global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     static_assert(C::BK == 32, "one 16x16x32 step per LDS tile");
-    typedef Stage<float, CS, true, FAST, AD, AMNC> SA;
-    typedef Stage<float, CS, false, FAST, BD, BMNC> SB;
+    typedef Stage<float, CS, true, FAST, AD, AMNC, C> SA;
+    typedef Stage<float, CS, false, FAST, BD, BMNC, C> SB;
+    constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef LayBF<AMNC, C::BM> LA;
     typedef LayBF<BMNC, C::BN> LB;
     static_assert(SA::TK == SB::TK, "A and B disagree on the k lowering");
@@ -80,17 +98,17 @@ __global__ __launch_bounds__(NT, 2) void md_bf16x3_kernel(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][LB::SIZE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
+    const int wm0 = (wave % C::WGM) * (C::BM / C::WGM), wn0 = (wave / C::WGM) * (C::BN / C::WGN);
     int tm, tn;
     map_tile(blockIdx.x, gridDim.x, g.tiles_m, g.tiles_n, &tm, &tn);
     const int64_t mn0a = (int64_t)tm * SA::TMN, mn0b = (int64_t)tn * SB::TMN;
     const int nk = (int)((g.k + SA::TK - 1) / SA::TK);
 
-    v4f acc[4][4];
+    v4f acc[WMB][WNB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < WMB; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+        for (int b = 0; b < WNB; ++b) acc[a][b] = v4f{0, 0, 0, 0};
 
     SA la(g, tid, mn0a);
     SB lb(g, tid, mn0b);
@@ -100,19 +118,22 @@ __global__ __launch_bounds__(NT, 2) void md_bf16x3_kernel(GemmArgs g) {
     };
     // One LDS tile = one 32-deep step: 3 bf16 MFMAs per 16x16 block.
     auto tile = [&](int cur, bool store_next) {
-        bf16x8 ah[4], al[4], bh[4], bl[4];
+        bf16x8 ah[WMB], al[WMB], bh[WNB], bl[WNB];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < WMB; ++i) {
             ah[i] = read_bf16_frag<AMNC, C::BM>(sA[cur][0], lane, wm0, i);
             al[i] = read_bf16_frag<AMNC, C::BM>(sA[cur][1], lane, wm0, i);
+        }
+#pragma unroll
+        for (int i = 0; i < WNB; ++i) {
             bh[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][0], lane, wn0, i);
             bl[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][1], lane, wn0, i);
         }
         if (store_next) stage_out(cur ^ 1);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < WMB; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < WNB; ++b) {
                 acc[a][b] = mfma_bf16(bl[b], ah[a], acc[a][b]);
                 acc[a][b] = mfma_bf16(bh[b], al[a], acc[a][b]);
                 acc[a][b] = mfma_bf16(bh[b], ah[a], acc[a][b]);
@@ -140,13 +161,13 @@ __global__ __launch_bounds__(NT, 2) void md_bf16x3_kernel(GemmArgs g) {
 
     const int ml = lane & 15;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < WNB; ++b) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int nl = acc_row<float>(lane, v);
             if constexpr (MDBL) {
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < WMB / 2; ++q) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
                     update_cplx<float>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
@@ -154,7 +175,7 @@ __global__ __launch_bounds__(NT, 2) void md_bf16x3_kernel(GemmArgs g) {
             } else if constexpr (NDBL) {
                 if ((b & 1) == 0) {
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
+                    for (int a = 0; a < WMB; ++a) {
                         const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                         const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
                         update_cplx<float>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
@@ -162,7 +183,7 @@ __global__ __launch_bounds__(NT, 2) void md_bf16x3_kernel(GemmArgs g) {
                 }
             } else {
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
+                for (int a = 0; a < WMB; ++a) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
                     if constexpr (CCPLX) update_cplx<float>(g, i, j, acc[a][b][v], 0.0f);

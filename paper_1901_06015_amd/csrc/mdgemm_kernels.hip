@@ -27,7 +27,11 @@ typedef float KT;
 template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC>
 static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 #if MD_KT == 2
-    hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+    if constexpr (tile_kind(PREC_BF16X3, CS, FAST) == 3)
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>>), dim3(nwg),
+                           dim3(Deep<float>::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
 #else
     constexpr int kind = tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST);
     if constexpr (kind == 1)
