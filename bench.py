@@ -157,15 +157,15 @@ def kernel_symbol(plan, transa="N", transb="N"):
     (plan kernel names read md_gemm_<prec>_case<c>_<path>_<A><B>_<tile>)."""
     parts = plan["kernel"].split("_")
     t = "double" if parts[2] == "f64" else "float"
-    fast = parts[4] == "fast"
+    fast, rag = parts[4] in ("fast", "ragged"), parts[4] == "ragged"
     ad, bd = parts[5][0] == "d", parts[5][1] == "d"
     cfg = {"t128x128w4": "TileCfg", "t128x256w8": "WideN", "t256x128w8": "WideM",
            "t128x128w8": "Deep"}[parts[6]]
     amnc = (transa == "N") if fast else True
     bmnc = (transb != "N") if fast else True
     b = lambda v: "true" if v else "false"
-    return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s, md::%s<%s> >(md::GemmArgs)" % (
-        t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc), cfg, t)
+    return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s, md::%s<%s>, %s>(md::GemmArgs)" % (
+        t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc), cfg, t, b(rag))
 
 
 def traffic_record(symbol):

@@ -62,7 +62,8 @@ struct GemmArgs {
     int a_dbl, b_dbl, c_dbl;  // storage precision is double
     int c_cplx;               // C is complex
     int ta, tb;               // 0 = 'N', 1 = 'T', 2 = 'C'
-    int a_vec, b_vec;         // 16-byte vector loads are aligned
+    int a_vec, b_vec;         // the operand can be staged in 16-byte chunks
+    int a_ragged, b_ragged;   // stored along k, its columns end inside a chunk (Stage::load_fast)
     int beta_zero;            // C is not read
     double alpha_re, alpha_im;
     double beta_re, beta_im;

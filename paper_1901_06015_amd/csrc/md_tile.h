@@ -149,7 +149,9 @@ __device__ __forceinline__ int split_pos(int mm, int q) { return (((mm >> 4) << 
 // !FAST: any alignment / leading dimension; the orientation comes from the
 //       trans argument at run time, components are loaded one by one and the
 //       LDS layout is [k][mn] (MNC must be true).
-template <class T, int CS, bool IS_A, bool FAST, bool SDBL, bool MNC, class C = TileCfg<T>>
+// RAG (fast path only): the operand's columns may end inside a chunk; an
+// operand stored contiguous along k then masks what a chunk reads past them.
+template <class T, int CS, bool IS_A, bool FAST, bool SDBL, bool MNC, class C = TileCfg<T>, bool RAG = false>
 struct Stage {
     static constexpr int MODE = mode_of<CS, IS_A>();
     static constexpr int W = (MODE == M_PLAIN) ? 1 : 2;  // stored components per element
@@ -207,7 +209,13 @@ struct Stage {
     }
 
     // FAST path: buffer loads.  A chunk outside the matrix gets an offset
-    // beyond the resource's range and reads as zero, with no branch.
+    // beyond the resource's range and reads as zero, with no branch.  When the
+    // stored columns end inside a chunk (RAG), a chunk can reach past its
+    // column's end into the next column, padding, or nothing.  Along m or n
+    // those components land in rows (columns) of the real product beyond the
+    // matrix, which feed only outputs the epilogue never writes; along k they
+    // would meet the other operand's k beyond the matrix, so there they are
+    // zeroed after the load.
     __device__ __forceinline__ void load_fast(int t) {
         const int64_t k0 = (int64_t)t * TK;
         const int64_t base_off = (MNC ? (k0 * ld + mn0) : (mn0 * ld + k0)) * W * ESZ;
@@ -229,7 +237,19 @@ struct Stage {
             const bool ok = (!PARTIAL || active) && (e_mn < mlim) && (e_k < klim);
             const uint32_t off = ok ? (uint32_t)col * col_bytes + (uint32_t)(pos * 16) : 0x80000000u;
             const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
-            raw[c] = make_uint4(x[0], x[1], x[2], x[3]);
+            uint4 v = make_uint4(x[0], x[1], x[2], x[3]);
+            if constexpr (RAG && !MNC) {
+                // components of this chunk inside its column
+                const int64_t lim = (int64_t)klim * W - pos * CW;
+                if constexpr (SDBL) {
+                    if (lim < 2) { v.z = 0u; v.w = 0u; }
+                } else {
+                    if (lim < 2) v.y = 0u;
+                    if (lim < 3) v.z = 0u;
+                    if (lim < 4) v.w = 0u;
+                }
+            }
+            raw[c] = v;
         }
     }
 
@@ -484,10 +504,11 @@ struct Frag {
 // faster for every configuration except FP64 on 4 waves (late store up to 5 %
 // faster there).
 
-template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<T>>
+template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<T>,
+          bool RAG = false>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
-    typedef Stage<T, CS, true, FAST, AD, AMNC, C> SA;
-    typedef Stage<T, CS, false, FAST, BD, BMNC, C> SB;
+    typedef Stage<T, CS, true, FAST, AD, AMNC, C, RAG> SA;
+    typedef Stage<T, CS, false, FAST, BD, BMNC, C, RAG> SB;
     constexpr bool PIPE = C::PIPE;
     constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef typename AccT<T>::type acc_t;

@@ -80,17 +80,20 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     g.a_dbl = dt_dbl(dta); g.b_dbl = dt_dbl(dtb); g.c_dbl = dt_dbl(dtc);
     g.c_cplx = dt_cplx(dtc);
     g.ta = ta; g.tb = tb;
-    // 16-byte loads need an aligned base and column stride, and columns whose
-    // length (in real components) is a multiple of four so that no chunk of
-    // four components straddles the end of a column.
+    // The fast kernels stage 16-byte chunks with buffer loads, which need only
+    // the 4-byte alignment every s/d/c/z array has.  An operand stored
+    // contiguous along k whose columns are not a whole number of chunks is
+    // "ragged": the components a chunk reads past a column's end are zeroed
+    // after the load (Stage::load_fast).
+    // They address a tile with 32-bit offsets from its origin: 128 columns of
+    // the operand must span less than 2 GiB.
     const int wa = dt_cplx(dta) ? 2 : 1, wb = dt_cplx(dtb) ? 2 : 1;
-    // The fast kernels address a tile with 32-bit offsets from its origin:
-    // 128 columns of the operand must span less than 2 GiB.
+    const int cwa = dt_dbl(dta) ? 2 : 4, cwb = dt_dbl(dtb) ? 2 : 4;  // components per chunk
     const int64_t max_ld = ((int64_t)1 << 31) / (128 * 16) - 64;
-    g.a_vec = ((uintptr_t)A % 16 == 0) && ((lda * dt_bytes(dta)) % 16 == 0) &&
-              (((ta == 0 ? m : k) * wa) % 4 == 0) && lda < max_ld;
-    g.b_vec = ((uintptr_t)B % 16 == 0) && ((ldb * dt_bytes(dtb)) % 16 == 0) &&
-              (((tb == 0 ? k : n) * wb) % 4 == 0) && ldb < max_ld;
+    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld;
+    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld;
+    g.a_ragged = ta != 0 && (k * wa) % cwa != 0;
+    g.b_ragged = tb == 0 && (k * wb) % cwb != 0;
     g.alpha_re = are; g.alpha_im = aim;
     g.beta_re = bre; g.beta_im = bim;
     g.beta_zero = (bre == 0.0 && bim == 0.0);

@@ -24,57 +24,67 @@ typedef double KT;
 typedef float KT;
 #endif
 
-template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC>
+template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, bool RAG>
 static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 #if MD_KT == 2
     if constexpr (tile_kind(PREC_BF16X3, CS, FAST) == 3)
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>>), dim3(nwg),
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG>), dim3(nwg),
                            dim3(Deep<float>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, TileCfg<float>, RAG>), dim3(nwg),
+                           dim3(NT), 0, s, a);
 #else
     constexpr int kind = tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST);
     if constexpr (kind == 1)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideN<KT>>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideN<KT>, RAG>), dim3(nwg),
                            dim3(WideN<KT>::NT), 0, s, a);
     else if constexpr (kind == 2)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideM<KT>>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideM<KT>, RAG>), dim3(nwg),
                            dim3(WideM<KT>::NT), 0, s, a);
     else if constexpr (kind == 3)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, Deep<KT>>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, Deep<KT>, RAG>), dim3(nwg),
                            dim3(Deep<KT>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC>), dim3(nwg), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, TileCfg<KT>, RAG>), dim3(nwg),
+                           dim3(NT), 0, s, a);
 #endif
 }
 
-template <int CS, bool FAST, bool AMNC, bool BMNC>
+template <int CS, bool FAST, bool AMNC, bool BMNC, bool RAG>
 static void launch_v(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     if (a.a_dbl) {
-        if (a.b_dbl) launch_k<CS, FAST, true, true, AMNC, BMNC>(a, s, nwg);
-        else launch_k<CS, FAST, true, false, AMNC, BMNC>(a, s, nwg);
+        if (a.b_dbl) launch_k<CS, FAST, true, true, AMNC, BMNC, RAG>(a, s, nwg);
+        else launch_k<CS, FAST, true, false, AMNC, BMNC, RAG>(a, s, nwg);
     } else {
-        if (a.b_dbl) launch_k<CS, FAST, false, true, AMNC, BMNC>(a, s, nwg);
-        else launch_k<CS, FAST, false, false, AMNC, BMNC>(a, s, nwg);
+        if (a.b_dbl) launch_k<CS, FAST, false, true, AMNC, BMNC, RAG>(a, s, nwg);
+        else launch_k<CS, FAST, false, false, AMNC, BMNC, RAG>(a, s, nwg);
     }
 }
 
 // The fast kernels take the operands' orientation (A contiguous along m for
-// 'N', B contiguous along n for 'T'/'C') as template parameters; the generic
-// kernels read it from the arguments.
+// 'N', B contiguous along n for 'T'/'C') as template parameters, and a ragged
+// variant for operands stored along k whose columns end inside a chunk (never
+// the case when both are stored along m/n); the generic kernels read the
+// orientation from the arguments.
 template <int CS>
 static void launch_c(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     if (a.a_vec && a.b_vec) {
-        const bool am = a.ta == 0, bm = a.tb != 0;
+        const bool am = a.ta == 0, bm = a.tb != 0, rag = a.a_ragged || a.b_ragged;
         if (am) {
-            if (bm) launch_v<CS, true, true, true>(a, s, nwg);
-            else launch_v<CS, true, true, false>(a, s, nwg);
+            if (bm) launch_v<CS, true, true, true, false>(a, s, nwg);
+            else if (rag) launch_v<CS, true, true, false, true>(a, s, nwg);
+            else launch_v<CS, true, true, false, false>(a, s, nwg);
         } else {
-            if (bm) launch_v<CS, true, false, true>(a, s, nwg);
-            else launch_v<CS, true, false, false>(a, s, nwg);
+            if (bm) {
+                if (rag) launch_v<CS, true, false, true, true>(a, s, nwg);
+                else launch_v<CS, true, false, true, false>(a, s, nwg);
+            } else {
+                if (rag) launch_v<CS, true, false, false, true>(a, s, nwg);
+                else launch_v<CS, true, false, false, false>(a, s, nwg);
+            }
         }
     } else {
-        launch_v<CS, false, true, true>(a, s, nwg);
+        launch_v<CS, false, true, true, false>(a, s, nwg);
     }
 }
 

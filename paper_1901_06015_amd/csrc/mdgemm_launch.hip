@@ -98,7 +98,8 @@ void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len) {
     static const char *tiles[4] = {"t128x128w4", "t128x256w8", "t256x128w8", "t128x128w8"};
     const int kind = tile_kind(prec, cs, a.a_vec && a.b_vec);
     snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c_%s", prec == PREC_D ? "f64" : (prec == PREC_S ? "f32" : "bf16x3"),
-             (cs >= 0 && cs < 8) ? cases[cs] : "?", (a.a_vec && a.b_vec) ? "fast" : "generic",
+             (cs >= 0 && cs < 8) ? cases[cs] : "?",
+             (a.a_vec && a.b_vec) ? ((a.a_ragged || a.b_ragged) ? "ragged" : "fast") : "generic",
              a.a_dbl ? 'd' : 's', a.b_dbl ? 'd' : 's', tiles[kind]);
 }
 

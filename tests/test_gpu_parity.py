@@ -207,3 +207,11 @@ def test_bf16x3_transposes_and_loguniform():
             one(cab[0], cab[1], cab[2], 131, 97, 160, "bf16x3", transa, transb)
     for cab in ("sss", "css", "ccs", "ccc"):
         one(cab[0], cab[1], cab[2], 128, 128, 256, "bf16x3", dist="loguniform", beta=0.0)
+
+
+def test_huge_leading_dimension_generic_path():
+    """A leading dimension of 2^20 or more keeps the kernels' 32-bit tile
+    offsets from fitting: the component-wise path takes over, with the same
+    result."""
+    for cab, comp in (("zcd", "d"), ("sds", "s")):
+        one(cab[0], cab[1], cab[2], 40, 24, 8, comp, pad_a=(1 << 20) - 40 + 8)
