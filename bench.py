@@ -57,7 +57,7 @@ def parse():
     p.add_argument("--slots", type=int, default=4, help="serving: concurrent batches (streams)")
     p.add_argument("--max-batch", type=int, default=64, help="serving: requests per grouped launch")
     p.add_argument("--big-gflop", type=float, default=2.0, help="serving: requests above this run alone")
-    p.add_argument("--big-lanes", type=int, default=1, help="serving: large requests running at once")
+    p.add_argument("--big-lanes", type=int, default=2, help="serving: large requests running at once")
     p.add_argument("--no-plain-stream", action="store_true",
                    help="serving: skip the plain-form run of the same arrival stream")
     p.add_argument("--workload", default="sweep", choices=["sweep", "precision", "grouped", "serving"],
