@@ -15,9 +15,13 @@ Reported (one JSON line):
                computation precision; torch.matmul -> hipBLASLt/rocBLAS)
   roofline     dominant kernel's achieved TFLOP/s (algorithmic flops / its
                measured duration, HIP events on its stream) vs the MFMA peak
+  per_combo.speedup_vs_adhoc
+               time of the ad-hoc alternative (cast and copy every operand to
+               the domain's computation type with torch, vendor GEMM, update,
+               cast back) over mdgemm's
   cpu_baseline the FP64 oracle timed on this host on a bounded sample
 
-    python bench.py [--steps K] [--warmup W] [--size N] [--combos zcd,sss] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--size N] [--combos zcd,sss] [--no-cpu] [--no-adhoc]
 """
 import argparse
 import hashlib
@@ -46,6 +50,7 @@ def parse():
     p.add_argument("--combos", type=str, default="", help="comma list like zcdd,ssss (cabx)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-native", action="store_true")
+    p.add_argument("--no-adhoc", action="store_true", help="skip the ad-hoc (cast, copy, vendor GEMM) baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain copy kernel of known size (HBM counter calibration)")
@@ -125,6 +130,45 @@ def native_times(n, reps=20):
         res[name] = {"p50_s": float(np.median(ts)), "gflops": fl * n ** 3 / float(np.median(ts)) / 1e9}
         del a, b, c
         torch.cuda.empty_cache()
+    return res
+
+
+def adhoc_times(ops, todo, reps=3):
+    """p50 seconds of the ad-hoc alternative for each combination: cast and
+    copy A, B and C to the computation type of the product's domain (complex
+    when any operand is complex), one vendor GEMM (torch.matmul), then
+    beta*C + alpha*AB and the cast back to C's storage type (Re for a real
+    C), all with torch on the device.  A timing baseline only: it spends the
+    flops of the common domain and the traffic of the casts and copies that
+    the in-kernel cast avoids (and rounds beta*C in the computation precision,
+    not C's).  It works on a copy of C."""
+    import torch
+    res = {}
+    for cabx in todo:
+        tc, ta, tb, x = cabx
+        cplx = any(t in "cz" for t in (tc, ta, tb))
+        T = {(False, "s"): torch.float32, (False, "d"): torch.float64,
+             (True, "s"): torch.complex64, (True, "d"): torch.complex128}[(cplx, x)]
+        A, B, C = ops["A" + ta], ops["B" + tb], ops["C" + tc].clone()
+
+        def run():
+            R = (-0.5) * C.to(T) + 1.5 * torch.matmul(A.to(T), B.to(T))
+            C.copy_(R.real if (R.is_complex() and not C.is_complex()) else R)
+
+        run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        res[cabx] = float(np.median(ts))
+        del C
+    torch.cuda.empty_cache()
     return res
 
 
@@ -767,6 +811,7 @@ def main():
     value = step_flops / (ms / 1e3) / 1e9
 
     native = native_times(n) if not args.no_native else {}
+    adhoc = adhoc_times(ops, todo) if not args.no_adhoc else {}
     if args.calibrate_copy:
         copy_calibration()
     per = {}
@@ -779,6 +824,9 @@ def main():
         per[c] = {"case": plans[c]["case"], "gflops": round(gf, 1),
                   "vs_native": round(gf / nat["gflops"], 3) if nat else None,
                   "p50_ms": round(p50 * 1e3, 4), "p99_ms": round(float(np.percentile(ts, 99)) * 1e3, 4)}
+        if c in adhoc:
+            per[c]["adhoc_ms"] = round(adhoc[c] * 1e3, 4)
+            per[c]["speedup_vs_adhoc"] = round(adhoc[c] / p50, 3)
         k = kernel_symbol(plans[c])
         bk = by_kernel.setdefault(k, {"flops": 0.0, "time": 0.0, "launches": 0, "bytes": 0.0})
         bk["flops"] += flops[c] * len(ts)
@@ -813,6 +861,10 @@ def main():
                       "median": float(np.median(ratios)) if ratios else None,
                       "combos_at_or_above_0.9": sum(1 for r in ratios if r >= 0.9)},
         "native_gflops": {k: round(v["gflops"], 1) for k, v in native.items()},
+        "vs_adhoc": ({"median_speedup": float(np.median([v["speedup_vs_adhoc"] for v in per.values()])),
+                      "min_speedup": min(v["speedup_vs_adhoc"] for v in per.values()),
+                      "method": "cast+copy to the domain's computation type, torch.matmul, update, cast back"}
+                     if adhoc else None),
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
                      "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_TFLOPS[prec], 4),
