@@ -54,6 +54,9 @@ class Oracle:
         lib.md_oracle_gemm.restype = ci
         lib.md_oracle_gemm_at.argtypes = common + [i64, vp, vp, vp, vp]
         lib.md_oracle_gemm_at.restype = ci
+        lib.md_oracle_gemm_gs.argtypes = [cc, cc, i64, i64, i64, dbl, dbl, vp, ci, i64, i64, vp, ci, i64, i64,
+                                          dbl, dbl, vp, ci, i64, i64, vp, vp]
+        lib.md_oracle_gemm_gs.restype = ci
         lib.md_oracle_case.argtypes = [ci, ci, ci]
         lib.md_oracle_case.restype = ci
         lib.md_oracle_flops.argtypes = [ci, ci, ci, i64, i64, i64]
@@ -105,6 +108,22 @@ class Oracle:
                                         rows.shape[0], rows.ctypes.data, cols.ctypes.data,
                                         out.ctypes.data, g.ctypes.data)
         return st, out, g
+
+
+    def gemm_gs(self, transa, transb, m, n, k, alpha, A, dta, rsa, csa, B, dtb, rsb, csb,
+                beta, C, dtc, rsc, csc, want_bound=True):
+        """The definition with row/column strides (elements) for every operand:
+        A, B, C are flat numpy buffers of their storage type.  Returns (status,
+        cref complex128 (m, n), g float64 (m, n))."""
+        alpha, beta = complex(alpha), complex(beta)
+        cref = np.zeros((max(m, 0), max(n, 0)), dtype=np.complex128, order="F")
+        g = np.zeros((max(m, 0), max(n, 0)), dtype=np.float64, order="F") if want_bound else None
+        ptr = lambda X: None if X is None else X.ctypes.data
+        st = self.lib.md_oracle_gemm_gs(transa.encode(), transb.encode(), m, n, k, alpha.real, alpha.imag,
+                                        ptr(A), tag(dta), rsa, csa, ptr(B), tag(dtb), rsb, csb,
+                                        beta.real, beta.imag, ptr(C), tag(dtc), rsc, csc,
+                                        cref.ctypes.data, g.ctypes.data if g is not None else None)
+        return st, cref, g
 
 
 _default = None

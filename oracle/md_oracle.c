@@ -7,7 +7,11 @@
  *
  *   1. every stored element is promoted exactly to complex double (a real
  *      operand has imaginary part 0; float -> double is exact);
- *   2. op(X) is X, X^T or X^H (Section 1, the nine BLAS variants);
+ *   2. op(X) is X, X^T, X^H (Section 1, the nine BLAS variants) or conj(X),
+ *      the conjugation without transposition of the paper's hypothetical
+ *      API (Section 2); an element (r, c) of a stored operand lies at
+ *      r * rstride + c * cstride elements from its origin, the row and
+ *      column strides of that API (column-major: rstride 1, cstride = ld);
  *   3. for every (i, j) the sum over p runs in ascending order with the
  *      complex product written out in real arithmetic;
  *   4. the scalars follow Section 6: alpha is used as given (a complex alpha
@@ -36,11 +40,12 @@
 static int tag_ok(int dt) { return dt >= T_S && dt <= T_Z; }
 static int tag_complex(int dt) { return dt == T_C || dt == T_Z; }
 
-/* Promote stored element (r, c) of a column-major matrix exactly to (re, im). */
-static void fetch(const void *X, int dt, int64_t ld, int64_t r, int64_t c,
+/* Promote stored element (r, c) exactly to (re, im); (rs, cs) are the row and
+ * column strides in elements of the operand's own type. */
+static void fetch(const void *X, int dt, int64_t rs, int64_t cs, int64_t r, int64_t c,
                   double *re, double *im)
 {
-    int64_t idx = r + c * ld;
+    int64_t idx = r * rs + c * cs;
     if (dt == T_S) {
         *re = (double)((const float *)X)[idx];
         *im = 0.0;
@@ -56,17 +61,17 @@ static void fetch(const void *X, int dt, int64_t ld, int64_t r, int64_t c,
     }
 }
 
-/* Element (i, p) of op(X): 'N' -> X(i,p); 'T' -> X(p,i); 'C' -> conj(X(p,i)). */
-static void fetch_op(char tr, const void *X, int dt, int64_t ld, int64_t i, int64_t p,
+/* Element (i, p) of op(X): 'N' -> X(i,p); 'R' -> conj(X(i,p));
+ * 'T' -> X(p,i); 'C' -> conj(X(p,i)). */
+static void fetch_op(char tr, const void *X, int dt, int64_t rs, int64_t cs, int64_t i, int64_t p,
                      double *re, double *im)
 {
-    if (tr == 'N') {
-        fetch(X, dt, ld, i, p, re, im);
-    } else {
-        fetch(X, dt, ld, p, i, re, im);
-        if (tr == 'C')
-            *im = -*im;
-    }
+    if (tr == 'N' || tr == 'R')
+        fetch(X, dt, rs, cs, i, p, re, im);
+    else
+        fetch(X, dt, rs, cs, p, i, re, im);
+    if (tr == 'C' || tr == 'R')
+        *im = -*im;
 }
 
 static char norm_trans(char t)
@@ -74,8 +79,11 @@ static char norm_trans(char t)
     if (t == 'n') return 'N';
     if (t == 't') return 'T';
     if (t == 'c') return 'C';
+    if (t == 'r') return 'R';
     return t;
 }
+
+static int trans_ok(char t) { return t == 'N' || t == 'T' || t == 'C' || t == 'R'; }
 
 int md_oracle_case(int dtc, int dta, int dtb)
 {
@@ -96,12 +104,11 @@ double md_oracle_flops(int dtc, int dta, int dtb, int64_t m, int64_t n, int64_t 
 static int check_args(char ta, char tb, int64_t m, int64_t n, int64_t k,
                       int dta, int64_t lda, int dtb, int64_t ldb, int dtc, int64_t ldc)
 {
-    if (ta != 'N' && ta != 'T' && ta != 'C') return ORACLE_ERR_ARG;
-    if (tb != 'N' && tb != 'T' && tb != 'C') return ORACLE_ERR_ARG;
+    if (!trans_ok(ta) || !trans_ok(tb)) return ORACLE_ERR_ARG;
     if (m < 0 || n < 0 || k < 0) return ORACLE_ERR_ARG;
     if (!tag_ok(dta) || !tag_ok(dtb) || !tag_ok(dtc)) return ORACLE_ERR_ARG;
-    int64_t arows = (ta == 'N') ? m : k;
-    int64_t brows = (tb == 'N') ? k : n;
+    int64_t arows = (ta == 'N' || ta == 'R') ? m : k;
+    int64_t brows = (tb == 'N' || tb == 'R') ? k : n;
     if (lda < (arows > 1 ? arows : 1)) return ORACLE_ERR_ARG;
     if (ldb < (brows > 1 ? brows : 1)) return ORACLE_ERR_ARG;
     if (ldc < (m > 1 ? m : 1)) return ORACLE_ERR_ARG;
@@ -118,10 +125,10 @@ static int alpha_refused(int dtc, int dta, int dtb, double alpha_im)
 /* One entry of the result: the definition, for C(i, j). */
 static void entry(char ta, char tb, int64_t k,
                   double alpha_re, double alpha_im,
-                  const void *A, int dta, int64_t lda,
-                  const void *B, int dtb, int64_t ldb,
+                  const void *A, int dta, int64_t rsa, int64_t csa,
+                  const void *B, int dtb, int64_t rsb, int64_t csb,
                   double beta_re, double beta_im,
-                  const void *C, int dtc, int64_t ldc,
+                  const void *C, int dtc, int64_t rsc, int64_t csc,
                   int64_t i, int64_t j, double *out_re, double *out_im, double *out_g)
 {
     double sr = 0.0, si = 0.0, g = 0.0;
@@ -132,8 +139,8 @@ static void entry(char ta, char tb, int64_t k,
     if (use_ab) {
         for (int64_t p = 0; p < k; ++p) {
             double ar, ai, br, bi;
-            fetch_op(ta, A, dta, lda, i, p, &ar, &ai);
-            fetch_op(tb, B, dtb, ldb, p, j, &br, &bi);
+            fetch_op(ta, A, dta, rsa, csa, i, p, &ar, &ai);
+            fetch_op(tb, B, dtb, rsb, csb, p, j, &br, &bi);
             sr += ar * br - ai * bi;
             si += ar * bi + ai * br;
             g += sqrt(ar * ar + ai * ai) * sqrt(br * br + bi * bi);
@@ -149,7 +156,7 @@ static void entry(char ta, char tb, int64_t k,
     double rr = tr, ri = ti;
     if (bre != 0.0 || bim != 0.0) {
         double cr, ci;
-        fetch(C, dtc, ldc, i, j, &cr, &ci);
+        fetch(C, dtc, rsc, csc, i, j, &cr, &ci);
         rr = bre * cr - bim * ci + tr;
         ri = bre * ci + bim * cr + ti;
     }
@@ -173,8 +180,8 @@ int md_oracle_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
     for (int64_t j = 0; j < n; ++j) {
         for (int64_t i = 0; i < m; ++i) {
             int64_t o = i + j * m;
-            entry(ta, tb, k, alpha_re, alpha_im, A, dta, lda, B, dtb, ldb,
-                  beta_re, beta_im, C, dtc, ldc, i, j,
+            entry(ta, tb, k, alpha_re, alpha_im, A, dta, 1, lda, B, dtb, 1, ldb,
+                  beta_re, beta_im, C, dtc, 1, ldc, i, j,
                   &cref[2 * o], &cref[2 * o + 1], g ? &g[o] : NULL);
         }
     }
@@ -196,9 +203,34 @@ int md_oracle_gemm_at(char transa, char transb, int64_t m, int64_t n, int64_t k,
     if (alpha_refused(dtc, dta, dtb, alpha_im)) return ORACLE_ERR_ALPHA_IMAG;
     for (int64_t t = 0; t < count; ++t) {
         if (rows[t] < 0 || rows[t] >= m || cols[t] < 0 || cols[t] >= n) return ORACLE_ERR_ARG;
-        entry(ta, tb, k, alpha_re, alpha_im, A, dta, lda, B, dtb, ldb,
-              beta_re, beta_im, C, dtc, ldc, rows[t], cols[t],
+        entry(ta, tb, k, alpha_re, alpha_im, A, dta, 1, lda, B, dtb, 1, ldb,
+              beta_re, beta_im, C, dtc, 1, ldc, rows[t], cols[t],
               &cref[2 * t], &cref[2 * t + 1], g ? &g[t] : NULL);
+    }
+    return ORACLE_OK;
+}
+
+int md_oracle_gemm_gs(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                      double alpha_re, double alpha_im,
+                      const void *A, int dta, int64_t rsa, int64_t csa,
+                      const void *B, int dtb, int64_t rsb, int64_t csb,
+                      double beta_re, double beta_im,
+                      const void *C, int dtc, int64_t rsc, int64_t csc,
+                      double *cref, double *g)
+{
+    char ta = norm_trans(transa), tb = norm_trans(transb);
+    if (!trans_ok(ta) || !trans_ok(tb)) return ORACLE_ERR_ARG;
+    if (m < 0 || n < 0 || k < 0) return ORACLE_ERR_ARG;
+    if (!tag_ok(dta) || !tag_ok(dtb) || !tag_ok(dtc)) return ORACLE_ERR_ARG;
+    if (rsa < 1 || csa < 1 || rsb < 1 || csb < 1 || rsc < 1 || csc < 1) return ORACLE_ERR_ARG;
+    if (alpha_refused(dtc, dta, dtb, alpha_im)) return ORACLE_ERR_ALPHA_IMAG;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            int64_t o = i + j * m;
+            entry(ta, tb, k, alpha_re, alpha_im, A, dta, rsa, csa, B, dtb, rsb, csb,
+                  beta_re, beta_im, C, dtc, rsc, csc, i, j,
+                  &cref[2 * o], &cref[2 * o + 1], g ? &g[o] : NULL);
+        }
     }
     return ORACLE_OK;
 }

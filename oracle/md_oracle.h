@@ -13,7 +13,9 @@
  *
  * Storage tags: 0 = s (float), 1 = d (double), 2 = c (float complex,
  * interleaved re,im), 3 = z (double complex, interleaved).  Matrices are
- * column-major; a leading dimension counts elements of the operand's own type.
+ * column-major unless strides are given (md_oracle_gemm_gs); a leading
+ * dimension or stride counts elements of the operand's own type.  Trans
+ * letters: N, T, C (the BLAS) and R (conjugate without transposing).
  */
 #ifndef MD_ORACLE_H
 #define MD_ORACLE_H
@@ -60,6 +62,19 @@ int md_oracle_gemm_at(char transa, char transb, int64_t m, int64_t n, int64_t k,
                       double beta_re, double beta_im,
                       const void *C, int dtc, int64_t ldc,
                       int64_t count, const int64_t *rows, const int64_t *cols,
+                      double *cref, double *g);
+
+/* The same definition with every operand addressed by its row and column
+ * strides (element (r, c) at r*rs + c*cs elements; the hypothetical API of
+ * Section 2: column-major, row-major or general storage), and trans letters
+ * N, T, C or R (conjugate without transposing).  cref and g are column-major
+ * m x n as in md_oracle_gemm.  Strides must be positive. */
+int md_oracle_gemm_gs(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                      double alpha_re, double alpha_im,
+                      const void *A, int dta, int64_t rsa, int64_t csa,
+                      const void *B, int dtb, int64_t rsb, int64_t csb,
+                      double beta_re, double beta_im,
+                      const void *C, int dtc, int64_t rsc, int64_t csc,
                       double *cref, double *g);
 
 #ifdef __cplusplus

@@ -61,18 +61,21 @@ def _dom_tags(is_cplx):
 
 
 def _op(X, rows, cols, trans):
-    """op(X) as a complex128 array of the promoted stored values."""
+    """op(X) as a complex128 array of the promoted stored values; "R" is the
+    conjugate without transposition of Section 2's hypothetical API."""
     M = np.asarray(X[:rows, :cols], dtype=np.complex128)
     if trans == "N":
         return M
+    if trans == "R":
+        return M.conj()
     if trans == "T":
         return M.T
     return M.conj().T
 
 
 def _operands(dta, dtb, dtc, m, n, k, ta, tb, seed, dist="uniform"):
-    ar, ac = (m, k) if ta == "N" else (k, m)
-    br, bc = (k, n) if tb == "N" else (n, k)
+    ar, ac = (m, k) if ta in "NR" else (k, m)
+    br, bc = (k, n) if tb in "NR" else (n, k)
     A = inputs.matrix(ar, ac, dta, seed + 1, dist=dist)
     B = inputs.matrix(br, bc, dtb, seed + 2, dist=dist)
     C = inputs.matrix(m, n, dtc, seed + 3, dist=dist)
@@ -107,10 +110,11 @@ def pin_flops(o):
 
 
 def pin_same_type(o):
-    """Homogeneous storage is an ordinary GEMM: compare with numpy.matmul."""
+    """Homogeneous storage is an ordinary GEMM: compare with numpy.matmul, for
+    the nine BLAS op() pairs and those with R (conjugate, not transposed)."""
     fails = []
     for dt in TAGS:
-        for ta, tb in itertools.product("NTC", "NTC"):
+        for ta, tb in itertools.product("NTCR", "NTCR"):
             m, n, k = 5, 6, 7
             A, B, C, _, _ = _operands(dt, dt, dt, m, n, k, ta, tb, seed=11)
             alpha = 1.5 + (0.25j if dt in "cz" else 0)
@@ -381,9 +385,58 @@ def pin_transpose(o):
     return fails
 
 
+def _store(X, rows, cols, rs, cs, pad=777.25):
+    """A flat buffer holding the rows x cols block of X at r*rs + c*cs; the
+    other elements hold `pad`, so reading a wrong element changes the result."""
+    size = (rows - 1) * rs + (cols - 1) * cs + 1 if rows and cols else 1
+    buf = np.full(size, pad, dtype=X.dtype)
+    for r in range(rows):
+        for c in range(cols):
+            buf[r * rs + c * cs] = X[r, c]
+    return buf
+
+
+def pin_strides(o):
+    """Section 2's row and column strides: the same logical operands stored
+    column-major, row-major and in general storage (neither stride 1) give
+    numpy's product for homogeneous storage, and bitwise the column-major
+    result for mixed storage."""
+    fails = []
+    m, n, k = 5, 4, 3
+    layouts = {"col": lambda r, c: (1, r + 2), "row": lambda r, c: (c + 3, 1), "gen": lambda r, c: (2, 2 * r + 3)}
+    for dta, dtb, dtc, ta, tb in (("z", "z", "z", "N", "R"), ("d", "d", "d", "T", "N"), ("c", "s", "z", "C", "T"),
+                                   ("s", "z", "c", "R", "C"), ("z", "c", "d", "N", "N")):
+        A, B, C, ar, br = _operands(dta, dtb, dtc, m, n, k, ta, tb, seed=61)
+        ac, bc = A.shape[1], B.shape[1]
+        st0, ref0, _ = _call(o, ta, tb, m, n, k, 1.5, A, dta, B, dtb, -0.5, C, dtc)
+        same = dta == dtb == dtc
+        ref = None
+        if same:
+            ref = 1.5 * (_op(A, ar, ac, ta) @ _op(B, br, bc, tb)) - 0.5 * np.asarray(C, dtype=np.complex128)
+            if dtc in "sd":
+                ref = ref.real.astype(np.complex128)
+        for la, lb, lc in (("row", "row", "row"), ("gen", "col", "row"), ("col", "gen", "gen"), ("row", "gen", "col")):
+            rsa, csa = layouts[la](ar, ac)
+            rsb, csb = layouts[lb](br, bc)
+            rsc, csc = layouts[lc](m, n)
+            st, got, g = o.gemm_gs(ta, tb, m, n, k, 1.5, _store(A, ar, ac, rsa, csa), dta, rsa, csa,
+                                   _store(B, br, bc, rsb, csb), dtb, rsb, csb, -0.5,
+                                   _store(C, m, n, rsc, csc), dtc, rsc, csc)
+            what = "strides %s%s%s %s%s %s/%s/%s" % (dtc, dta, dtb, ta, tb, la, lb, lc)
+            if st != 0 or st0 != 0:
+                fails.append(what + " status %d/%d" % (st, st0))
+            elif same:
+                err = np.max(np.abs(got - ref) / (np.abs(g) + np.abs(ref) + 1e-300))
+                if not err < 1e-13:
+                    fails.append(what + " rel err %.3g" % err)
+            elif not np.array_equal(got, ref0):
+                fails.append(what + " differs from the column-major result")
+    return fails
+
+
 ALL_PINS = (pin_case_table, pin_flops, pin_same_type, pin_domain_identities,
             pin_exact_integers, pin_exact_rational, pin_1m_equations, pin_scalars,
-            pin_transpose)
+            pin_transpose, pin_strides)
 
 
 def run_all(o):

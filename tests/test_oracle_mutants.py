@@ -1,7 +1,8 @@
 """Plausible mistakes planted in copies of the oracle (on the CPU) must each be
 caught by at least one pin.  This shows the pins constrain every part of the
-definition: sign and index of each term, transposition, conjugation, the
-scalar policies and the real-C projection."""
+definition: sign and index of each term, transposition, conjugation (with and
+without transposition), the strides, the scalar policies and the real-C
+projection."""
 import os
 import shutil
 
@@ -17,8 +18,11 @@ MUTANTS = {
     "im_sign": ("si += ar * bi + ai * br;", "si += ar * bi - ai * br;"),
     "im_term_dropped": ("si += ar * bi + ai * br;", "si += ar * bi;"),
     "no_conj": ("*im = -*im;", "(void)0;"),
-    "trans_ignored": ("fetch(X, dt, ld, p, i, re, im);", "fetch(X, dt, ld, i, p, re, im);"),
-    "index_transposed": ("int64_t idx = r + c * ld;", "int64_t idx = r * ld + c;"),
+    "trans_ignored": ("fetch(X, dt, rs, cs, p, i, re, im);", "fetch(X, dt, rs, cs, i, p, re, im);"),
+    "index_transposed": ("int64_t idx = r * rs + c * cs;", "int64_t idx = r * cs + c * rs;"),
+    "row_stride_ignored": ("int64_t idx = r * rs + c * cs;", "int64_t idx = r + c * cs;"),
+    "r_op_not_conjugated": ("if (tr == 'C' || tr == 'R')", "if (tr == 'C')"),
+    "r_op_transposed": ("if (tr == 'N' || tr == 'R')", "if (tr == 'N')"),
     "alpha_cross_sign": ("double tr = use_ab ? alpha_re * sr - alpha_im * si : 0.0;",
                          "double tr = use_ab ? alpha_re * sr + alpha_im * si : 0.0;"),
     "beta_imag_kept_for_real_c": ("double bim = tag_complex(dtc) ? beta_im : 0.0;",
