@@ -205,8 +205,8 @@ def kernel_symbol(plan, transa="N", transb="N"):
     ad, bd = parts[5][0] == "d", parts[5][1] == "d"
     cfg = {"t128x128w4": "TileCfg", "t128x256w8": "WideN", "t256x128w8": "WideM",
            "t128x128w8": "Deep"}[parts[6]]
-    amnc = (transa == "N") if fast else True
-    bmnc = (transb != "N") if fast else True
+    amnc = (transa in "NR") if fast else True
+    bmnc = (transb in "TC") if fast else True
     b = lambda v: "true" if v else "false"
     return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s, md::%s<%s>, %s>(md::GemmArgs)" % (
         t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc), cfg, t, b(rag))

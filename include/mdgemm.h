@@ -80,8 +80,10 @@ typedef enum {
  * mdgemm -- one mixed-datatype product.
  *
  * Arguments (position in parentheses is the one reported as -i on error):
- *  (1) transa, (2) transb : 'N', 'T' or 'C' (lower case accepted); 'C' on a
- *        real operand equals 'T'.
+ *  (1) transa, (2) transb : 'N', 'T', 'C' (the BLAS) or 'R' (conjugate
+ *        without transposing, the fourth value of the paper's hypothetical
+ *        API, Section 2); lower case accepted.  On a real operand 'C' equals
+ *        'T' and 'R' equals 'N'.
  *  (3) m, (4) n, (5) k     : op(A) is m x k, op(B) is k x n, C is m x n; >= 0.
  *  (6) alpha               : cast to the computation precision (Section 6.1,
  *        option 1).  Im(alpha) is ignored in case 0 and used in case 3; in the
@@ -107,6 +109,34 @@ int mdgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
            md_scalar beta,
            void *C, md_dt dtc, int64_t ldc,
            md_comp comp, void *stream);
+
+/*
+ * mdgemm_strided -- the same product with every operand addressed by its row
+ * and column strides (element (i, j) of a stored operand at i*rs + j*cs
+ * elements of its type), the storage description of the paper's hypothetical
+ * API (Section 2; Section 3.3 for BLIS's row and column strides).  Strides are
+ * >= 1 and an operand's elements must not overlap: its columns lie apart
+ * (cs >= rs*rows; column-major storage is rs == 1) or its rows do
+ * (rs >= cs*cols; row-major storage is cs == 1); a stride along an extent of
+ * one element is not used.  Each operand is laid out independently:
+ *   - column-major and row-major operands run on the same kernels as mdgemm:
+ *     a row-major operand is its transpose stored column-major (its op flips
+ *     N <-> T, R <-> C), and a row-major C is computed as
+ *     C^T = op(B)^T op(A)^T;
+ *   - general storage (neither stride 1) takes the component-wise loads,
+ *     which read each element where its strides put it (slower: no 16-byte
+ *     chunks).
+ * Results follow mdgemm's rules.  Argument positions for errors: (1) transa
+ * (2) transb (3) m (4) n (5) k (6) alpha (7) A (8) dta (9) rsa (10) csa
+ * (11) B (12) dtb (13) rsb (14) csb (15) beta (16) C (17) dtc (18) rsc
+ * (19) csc (20) comp (21) stream; overlapping strides name the column stride
+ * when rs <= cs, else the row stride.
+ */
+int mdgemm_strided(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
+                   const void *A, md_dt dta, int64_t rsa, int64_t csa,
+                   const void *B, md_dt dtb, int64_t rsb, int64_t csb,
+                   md_scalar beta, void *C, md_dt dtc, int64_t rsc, int64_t csc,
+                   md_comp comp, void *stream);
 
 /* What mdgemm would do with the same arguments, computed on the host only
  * (no device call, usable without a GPU). */

@@ -62,6 +62,9 @@ def lib():
         L.mdgemm.argtypes = args + [vp]
         L.mdgemm.restype = ci
         L.mdgemm_plan.argtypes = args + [ctypes.POINTER(MdPlan)]
+        L.mdgemm_strided.argtypes = [cc, cc, i64, i64, i64, MdScalar, vp, ci, i64, i64, vp, ci, i64, i64,
+                                     MdScalar, vp, ci, i64, i64, ci, vp]
+        L.mdgemm_strided.restype = ci
         L.mdgemm_plan.restype = ci
         L.mdgemm_grouped.argtypes = [i64, ctypes.POINTER(MdGemmDesc), vp]
         L.mdgemm_grouped.restype = ci
@@ -101,6 +104,14 @@ def mdgemm(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C, dt
     """The C entry point with raw device pointers (ints)."""
     return lib().mdgemm(_ch(transa), _ch(transb), m, n, k, scalar(alpha), A, tag(dta), lda,
                         B, tag(dtb), ldb, scalar(beta), C, tag(dtc), ldc, comp_tag(comp), stream)
+
+
+def mdgemm_strided(transa, transb, m, n, k, alpha, A, dta, rsa, csa, B, dtb, rsb, csb,
+                   beta, C, dtc, rsc, csc, comp=None, stream=None):
+    """The strided C entry point: each operand with its row and column strides."""
+    return lib().mdgemm_strided(_ch(transa), _ch(transb), m, n, k, scalar(alpha), A, tag(dta), rsa, csa,
+                                B, tag(dtb), rsb, csb, scalar(beta), C, tag(dtc), rsc, csc,
+                                comp_tag(comp), stream)
 
 
 def mdgemm_plan(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C, dtc, ldc,

@@ -1,11 +1,13 @@
 """Torch-facing wrappers over the C ABI (marshalling only).
 
-Matrices are passed as 2-D torch tensors in column-major layout
-(``stride(0) == 1``; the leading dimension is ``stride(1)``), the layout the
-BLAS interface of Section 1 of the paper prescribes.  A convenient way to make
-one is ``torch.empty((cols, ld), dtype=..., device="cuda").t()[:rows]``.
+``gemm`` takes 2-D torch tensors stored by columns (``stride(0) == 1``) or by
+rows (``stride(1) == 1``, torch's default) and passes their row and column
+strides to ``mdgemm_strided`` (the strided interface sketched in Section 2 of
+the paper).  ``plan`` and grouped calls take column-major tensors, the BLAS
+layout of Section 1 (leading dimension ``stride(1)``); ``colmajor`` makes one.
 The storage type follows the tensor dtype: float32 -> s, float64 -> d,
-complex64 -> c, complex128 -> z.
+complex64 -> c, complex128 -> z.  op is one of N, T, C (conjugate transpose)
+and R (conjugate without transposing).
 """
 import torch
 
@@ -50,9 +52,10 @@ def _layout(t, name):
 
 def _dims(A, B, C, transa, transb):
     m, n = C.shape
-    k = A.shape[1] if transa.upper() == "N" else A.shape[0]
-    am = A.shape[0] if transa.upper() == "N" else A.shape[1]
-    bk, bn = (B.shape[0], B.shape[1]) if transb.upper() == "N" else (B.shape[1], B.shape[0])
+    a_plain, b_plain = transa.upper() in ("N", "R"), transb.upper() in ("N", "R")
+    k = A.shape[1] if a_plain else A.shape[0]
+    am = A.shape[0] if a_plain else A.shape[1]
+    bk, bn = (B.shape[0], B.shape[1]) if b_plain else (B.shape[1], B.shape[0])
     if am != m or bn != n or bk != k:
         raise ValueError("shape mismatch: op(A) %dx%d, op(B) %dx%d, C %dx%d" % (am, k, bk, bn, m, n))
     return m, n, k
@@ -66,10 +69,22 @@ def _args(A, B, C, alpha, beta, transa, transb, comp):
     return (transa, transb, m, n, k, alpha, pa, dta, lda, pb, dtb, ldb, beta, pc, dtc, ldc, comp)
 
 
+def _strides(t, name):
+    """(pointer, type, row stride, column stride); a stride along an extent of
+    at most one element is never used and is passed as 1."""
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    rows, cols = t.shape
+    rs = t.stride(0) if rows > 1 else 1
+    cs = t.stride(1) if cols > 1 else 1
+    return t.data_ptr(), dt_of(t), rs, cs
+
+
 def gemm(A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", comp=None, stream=None):
     """C := beta*C + alpha*op(A)*op(B) on the GPU, enqueued on `stream` (default:
-    torch's current stream for C's device).  `comp` is None (C's precision),
-    "s", "d" or "bf16x3".  Returns C."""
+    torch's current stream for C's device).  Each tensor may be stored by rows
+    or by columns.  `comp` is None (C's precision), "s", "d" or "bf16x3".
+    Returns C."""
     for t, nm in ((A, "A"), (B, "B"), (C, "C")):
         if not t.is_cuda:
             raise ValueError("%s must be a device tensor" % nm)
@@ -77,7 +92,12 @@ def gemm(A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", comp=None, stream
         stream = torch.cuda.current_stream(C.device).cuda_stream
     elif hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
-    st = _lib.mdgemm(*_args(A, B, C, alpha, beta, transa, transb, comp), stream=stream)
+    pa, dta, rsa, csa = _strides(A, "A")
+    pb, dtb, rsb, csb = _strides(B, "B")
+    pc, dtc, rsc, csc = _strides(C, "C")
+    m, n, k = _dims(A, B, C, transa, transb)
+    st = _lib.mdgemm_strided(transa, transb, m, n, k, alpha, pa, dta, rsa, csa, pb, dtb, rsb, csb,
+                             beta, pc, dtc, rsc, csc, comp, stream=stream)
     if st != 0:
         raise MdgemmError(st)
     return C

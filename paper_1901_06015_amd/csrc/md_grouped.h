@@ -80,8 +80,8 @@ __device__ __forceinline__ GOp make_gop(const GemmArgs &g, int cs, bool is_a) {
     o.mode = mode_rt(cs, is_a);
     o.dbl = is_a ? g.a_dbl : g.b_dbl;
     o.cplx = o.mode != M_PLAIN;
-    o.mnc = is_a ? (tr == 0) : (tr != 0);
-    o.conj = tr == 2;
+    o.mnc = is_a ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2);
+    o.conj = tr >= 2;
     o.kneg = is_a;
     return o;
 }

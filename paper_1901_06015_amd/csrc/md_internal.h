@@ -58,10 +58,13 @@ struct GemmArgs {
     const void *Cin;        // where beta*C is read from: C itself for the in-place
                             // operation, another m x n array of C's type and ldc otherwise
     int64_t lda, ldb, ldc;  // in elements of each operand's own type
+    int64_t rsa, rsb, rsc;  // element stride along a stored column: 1, except for general
+                            // storage (Section 2 row and column strides), which only the
+                            // component-wise loads and their epilogue take
     int64_t m, n, k;
     int a_dbl, b_dbl, c_dbl;  // storage precision is double
     int c_cplx;               // C is complex
-    int ta, tb;               // 0 = 'N', 1 = 'T', 2 = 'C'
+    int ta, tb;               // 0 = 'N', 1 = 'T', 2 = 'C', 3 = 'R' (conjugate, not transposed)
     int a_vec, b_vec;         // the operand can be staged in 16-byte chunks
     int a_ragged, b_ragged;   // stored along k, its columns end inside a chunk (Stage::load_fast)
     int beta_zero;            // C is not read
@@ -104,9 +107,11 @@ struct Decision {
     GemmArgs g{};
 };
 
+// rsa/rsb/rsc: element stride along each stored column (1 for BLAS storage).
 Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
                 const void *A, int dta, int64_t lda, const void *B, int dtb, int64_t ldb,
-                md_scalar beta, void *C, int dtc, int64_t ldc, int comp);
+                md_scalar beta, void *C, int dtc, int64_t ldc, int comp,
+                int64_t rsa = 1, int64_t rsb = 1, int64_t rsc = 1);
 
 // Host-side launchers (defined in mdgemm_kernels.hip).
 int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out);

@@ -433,10 +433,11 @@ int md_server_submit(md_server *s, const md_request *r, int64_t *ticket) {
     // validate exactly as mdgemm would (no device work)
     md_plan p;
     const int64_t lda = A.rows > 0 ? A.rows : 1, ldb = B.rows > 0 ? B.rows : 1, ldc = r->m > 0 ? r->m : 1;
-    const int64_t arows = (r->transa == 'N' || r->transa == 'n') ? r->m : r->k;
-    const int64_t acols = (r->transa == 'N' || r->transa == 'n') ? r->k : r->m;
-    const int64_t brows = (r->transb == 'N' || r->transb == 'n') ? r->k : r->n;
-    const int64_t bcols = (r->transb == 'N' || r->transb == 'n') ? r->n : r->k;
+    // op 'N'/'R' reads A as m x k (B as k x n), 'T'/'C' as its transpose
+    const bool an = r->transa == 'N' || r->transa == 'n' || r->transa == 'R' || r->transa == 'r';
+    const bool bn = r->transb == 'N' || r->transb == 'n' || r->transb == 'R' || r->transb == 'r';
+    const int64_t arows = an ? r->m : r->k, acols = an ? r->k : r->m;
+    const int64_t brows = bn ? r->k : r->n, bcols = bn ? r->n : r->k;
     if (A.rows != arows || A.cols != acols) {
         s->st.refused++;
         return -9;

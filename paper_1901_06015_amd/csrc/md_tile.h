@@ -181,7 +181,7 @@ struct Stage {
     uint4 raw[PER];  // one tile's loads, held until converted
 
     const char *base;
-    int64_t ld, MN, K, mn0;
+    int64_t ld, rs, MN, K, mn0;  // rs: element stride along a stored column (generic path)
     int64_t total_bytes;  // extent of the stored matrix
     bool mn_contig, conj;
     int cpc_log;          // log2 of chunks per stored column inside a tile
@@ -191,9 +191,11 @@ struct Stage {
 
     __device__ __forceinline__ Stage(const GemmArgs &g, int tid, int64_t mn0_) {
         const int tr = IS_A ? g.ta : g.tb;
-        mn_contig = FAST ? MNC : (IS_A ? (tr == 0) : (tr != 0));
-        conj = (tr == 2);
+        // A is stored along m for 'N'/'R', B along n for 'T'/'C'
+        mn_contig = FAST ? MNC : (IS_A ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2));
+        conj = tr >= 2;
         ld = IS_A ? g.lda : g.ldb;
+        rs = IS_A ? g.rsa : g.rsb;
         MN = IS_A ? g.m : g.n;
         K = g.k;
         mn0 = mn0_;
@@ -254,29 +256,32 @@ struct Stage {
     }
 
     // Generic path: components loaded one by one; outside the matrix reads zero.
+    // Component x of a stored column sits at (x / W) * rs * W + x % W (x
+    // itself when the elements of a column are adjacent).
     __device__ __forceinline__ void load_generic(int t) {
         const int64_t k0 = (int64_t)t * TK;
         const int64_t rows_st = mn_contig ? MN : K, cols_st = mn_contig ? K : MN;
         const int64_t r0 = mn_contig ? mn0 : k0, c0 = mn_contig ? k0 : mn0;
-        const int64_t contig_len = rows_st * W, col_stride = ld * W;
+        const int64_t contig_len = rows_st * W, col_stride = ld * W, rsw = rs * W;
+        auto at = [&](int64_t x) { return (x / W) * rsw + x % W; };
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int64_t col = c0 + col0 + c * col_step, comp0 = r0 * W + pos * CW;
             const bool colok = (!PARTIAL || active) && col < cols_st;
-            const int64_t idx = col * col_stride + comp0;
+            const int64_t cbase = col * col_stride;
             if constexpr (SDBL) {
-                const uint2 *p = (const uint2 *)base + idx;
+                const uint2 *p = (const uint2 *)base + cbase;
                 uint2 e0 = make_uint2(0u, 0u), e1 = e0;
-                if (colok && comp0 + 0 < contig_len) e0 = p[0];
-                if (colok && comp0 + 1 < contig_len) e1 = p[1];
+                if (colok && comp0 + 0 < contig_len) e0 = p[at(comp0 + 0)];
+                if (colok && comp0 + 1 < contig_len) e1 = p[at(comp0 + 1)];
                 raw[c] = make_uint4(e0.x, e0.y, e1.x, e1.y);
             } else {
-                const uint32_t *p = (const uint32_t *)base + idx;
+                const uint32_t *p = (const uint32_t *)base + cbase;
                 uint32_t e0 = 0u, e1 = 0u, e2 = 0u, e3 = 0u;
-                if (colok && comp0 + 0 < contig_len) e0 = p[0];
-                if (colok && comp0 + 1 < contig_len) e1 = p[1];
-                if (colok && comp0 + 2 < contig_len) e2 = p[2];
-                if (colok && comp0 + 3 < contig_len) e3 = p[3];
+                if (colok && comp0 + 0 < contig_len) e0 = p[at(comp0 + 0)];
+                if (colok && comp0 + 1 < contig_len) e1 = p[at(comp0 + 1)];
+                if (colok && comp0 + 2 < contig_len) e2 = p[at(comp0 + 2)];
+                if (colok && comp0 + 3 < contig_len) e3 = p[at(comp0 + 3)];
                 raw[c] = make_uint4(e0, e1, e2, e3);
             }
         }
@@ -386,10 +391,17 @@ __device__ __forceinline__ void map_tile(int wg, int nwg, int tiles_m, int tiles
 // ---------------------------------------------------------------------------
 // Epilogue: C := beta*C + alpha*AB, rounded once to C's storage type
 // ---------------------------------------------------------------------------
-template <class T>
+// GS: C may have an element stride along its columns (general storage; only
+// the component-wise kernels are launched for it).
+template <bool GS>
+__device__ __forceinline__ int64_t c_offset(const GemmArgs &g, int64_t i, int64_t j) {
+    return (GS ? i * g.rsc : i) + j * g.ldc;
+}
+
+template <class T, bool GS = false>
 __device__ __forceinline__ void update_real(const GemmArgs &g, int64_t i, int64_t j, T acc) {
     if (i >= g.m || j >= g.n) return;
-    const int64_t off = i + j * g.ldc;
+    const int64_t off = c_offset<GS>(g, i, j);
     const T ax = (T)g.alpha_re;
     if (g.c_dbl) {
         double *c = (double *)g.C;
@@ -426,10 +438,10 @@ __device__ __forceinline__ void cupdate(const GemmArgs &g, W *c2, const W *cin2,
     }
 }
 
-template <class T>
+template <class T, bool GS = false>
 __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_t j, T re, T im) {
     if (i >= g.m || j >= g.n) return;
-    const int64_t off = 2 * (i + j * g.ldc);
+    const int64_t off = 2 * c_offset<GS>(g, i, j);
     const T ar = (T)g.alpha_re, ai = (T)g.alpha_im;
     if (g.c_dbl) {
         double *c = (double *)g.C + off;
@@ -607,7 +619,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                 for (int q = 0; q < WMB / 2; ++q) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    update_cplx<T>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
+                    update_cplx<T, !FAST>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
                 }
             } else if constexpr (NDBL) {
                 if ((b & 1) == 0) {
@@ -615,7 +627,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                     for (int a = 0; a < WMB; ++a) {
                         const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                         const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
-                        update_cplx<T>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
+                        update_cplx<T, !FAST>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
                     }
                 }
             } else {
@@ -623,8 +635,8 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                 for (int a = 0; a < WMB; ++a) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    if constexpr (CCPLX) update_cplx<T>(g, i, j, acc[a][b][v], (T)0);
-                    else update_real<T>(g, i, j, acc[a][b][v]);
+                    if constexpr (CCPLX) update_cplx<T, !FAST>(g, i, j, acc[a][b][v], (T)0);
+                    else update_real<T, !FAST>(g, i, j, acc[a][b][v]);
                 }
             }
         }

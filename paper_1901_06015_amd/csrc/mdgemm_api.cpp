@@ -15,11 +15,53 @@ int norm_trans(char t) {
     case 'N': case 'n': return 0;
     case 'T': case 't': return 1;
     case 'C': case 'c': return 2;
+    case 'R': case 'r': return 3;  // conjugate without transposing (Section 2's hypothetical API)
     }
     return -1;
 }
 
 bool dt_ok(int dt) { return dt >= MD_S && dt <= MD_Z; }
+
+// The op of an operand after swapping its row and column strides (its
+// transpose): N <-> T, R <-> C.
+char flip_op(char t) {
+    switch (t) {
+    case 'N': case 'n': return 'T';
+    case 'T': case 't': return 'N';
+    case 'C': case 'c': return 'R';
+    case 'R': case 'r': return 'C';
+    }
+    return t;
+}
+
+// A stored rows x cols block with row stride rs and column stride cs (in
+// elements), seen as a column-major matrix with leading dimension ld and
+// element stride rs along its columns: the block itself, or its transpose
+// (then the operand's op flips).  Its elements must not overlap, so either its
+// columns lie apart (cs >= rs*rows) or its rows do (rs >= cs*cols); the view
+// keeps columns (rows) as stored columns accordingly.  Returns 0, 1 (bad row
+// stride) or 2 (bad column stride).
+struct View {
+    int64_t ld, rs;
+    bool transposed;
+};
+int storage_view(int64_t rows, int64_t cols, int64_t rs, int64_t cs, View *v) {
+    if (rs < 1) return 1;
+    if (cs < 1) return 2;
+    if (rows <= 1) {  // one row: cols elements at stride cs
+        *v = View{cols > 1 ? cs : 1, 1, false};
+        return 0;
+    }
+    if (cols <= 1) {  // one column: rows elements at stride rs, read as one stored row
+        *v = View{rs, 1, true};
+        return 0;
+    }
+    const bool cols_apart = cs / rows >= rs, rows_apart = rs / cols >= cs;
+    if (cols_apart) *v = View{cs, rs, false};
+    else if (rows_apart) *v = View{rs, cs, true};
+    else return rs <= cs ? 2 : 1;
+    return 0;
+}
 bool dt_cplx(int dt) { return dt == MD_C || dt == MD_Z; }
 bool dt_dbl(int dt) { return dt == MD_D || dt == MD_Z; }
 int dt_bytes(int dt) { return dt == MD_S ? 4 : (dt == MD_Z ? 16 : 8); }
@@ -35,7 +77,8 @@ namespace md {
 
 Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
                 const void *A, int dta, int64_t lda, const void *B, int dtb, int64_t ldb,
-                md_scalar beta, void *C, int dtc, int64_t ldc, int comp) {
+                md_scalar beta, void *C, int dtc, int64_t ldc, int comp,
+                int64_t rsa, int64_t rsb, int64_t rsc) {
     Decision d;
     const int ta = norm_trans(transa), tb = norm_trans(transb);
     if (ta < 0) { d.status = -1; return d; }
@@ -46,13 +89,14 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     const bool uses_ab = m > 0 && n > 0 && k > 0 && (alpha.re != 0.0 || alpha.im != 0.0);
     if (uses_ab && A == nullptr) { d.status = -7; return d; }
     if (!dt_ok(dta)) { d.status = -8; return d; }
-    if (lda < max1(ta == 0 ? m : k)) { d.status = -9; return d; }
+    // a column of r elements at element stride rs spans rs*r elements
+    if (lda / rsa < max1((ta == 0 || ta == 3) ? m : k)) { d.status = -9; return d; }
     if (uses_ab && B == nullptr) { d.status = -10; return d; }
     if (!dt_ok(dtb)) { d.status = -11; return d; }
-    if (ldb < max1(tb == 0 ? k : n)) { d.status = -12; return d; }
+    if (ldb / rsb < max1((tb == 0 || tb == 3) ? k : n)) { d.status = -12; return d; }
     if (m > 0 && n > 0 && C == nullptr) { d.status = -14; return d; }
     if (!dt_ok(dtc)) { d.status = -15; return d; }
-    if (ldc < max1(m)) { d.status = -16; return d; }
+    if (ldc / rsc < max1(m)) { d.status = -16; return d; }
     if (comp != MD_COMP_DEFAULT && comp != MD_COMP_S && comp != MD_COMP_D && comp != MD_COMP_S_BF16X3) {
         d.status = -17;
         return d;
@@ -76,6 +120,7 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     GemmArgs &g = d.g;
     g.A = A; g.B = B; g.C = C; g.Cin = C;
     g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.rsa = rsa; g.rsb = rsb; g.rsc = rsc;
     g.m = m; g.n = n; g.k = k;
     g.a_dbl = dt_dbl(dta); g.b_dbl = dt_dbl(dtb); g.c_dbl = dt_dbl(dtc);
     g.c_cplx = dt_cplx(dtc);
@@ -90,10 +135,13 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     const int wa = dt_cplx(dta) ? 2 : 1, wb = dt_cplx(dtb) ? 2 : 1;
     const int cwa = dt_dbl(dta) ? 2 : 4, cwb = dt_dbl(dtb) ? 2 : 4;  // components per chunk
     const int64_t max_ld = ((int64_t)1 << 31) / (128 * 16) - 64;
-    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld;
-    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld;
-    g.a_ragged = ta != 0 && (k * wa) % cwa != 0;
-    g.b_ragged = tb == 0 && (k * wb) % cwb != 0;
+    // General storage (an element stride along the column, for any operand) takes
+    // the component-wise path.
+    const bool plain_c = rsc == 1;
+    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld && rsa == 1 && plain_c;
+    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld && rsb == 1 && plain_c;
+    g.a_ragged = (ta == 1 || ta == 2) && (k * wa) % cwa != 0;
+    g.b_ragged = (tb == 0 || tb == 3) && (k * wb) % cwb != 0;
     g.alpha_re = are; g.alpha_im = aim;
     g.beta_re = bre; g.beta_im = bim;
     g.beta_zero = (bre == 0.0 && bim == 0.0);
@@ -143,6 +191,48 @@ int mdgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar 
     const Decision d = decide(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C, dtc,
                               ldc, comp);
     return run_decision(d, stream);
+}
+
+int mdgemm_strided(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,
+                   const void *A, md_dt dta, int64_t rsa, int64_t csa,
+                   const void *B, md_dt dtb, int64_t rsb, int64_t csb,
+                   md_scalar beta, void *C, md_dt dtc, int64_t rsc, int64_t csc,
+                   md_comp comp, void *stream) {
+    const int ta = norm_trans(transa), tb = norm_trans(transb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const bool uses_ab = m > 0 && n > 0 && k > 0 && (alpha.re != 0.0 || alpha.im != 0.0);
+    if (uses_ab && A == nullptr) return -7;
+    if (!dt_ok(dta)) return -8;
+    if (uses_ab && B == nullptr) return -11;
+    if (!dt_ok(dtb)) return -12;
+    if (m > 0 && n > 0 && C == nullptr) return -16;
+    if (!dt_ok(dtc)) return -17;
+    if (comp != MD_COMP_DEFAULT && comp != MD_COMP_S && comp != MD_COMP_D && comp != MD_COMP_S_BF16X3) return -20;
+    // each operand as a column-major view: its stored block (rows x cols),
+    // or its transpose when its rows lie apart
+    const bool an = ta == 0 || ta == 3, bn = tb == 0 || tb == 3;
+    View va, vb, vc;
+    int st = storage_view(an ? m : k, an ? k : m, rsa, csa, &va);
+    if (st != 0) return st == 1 ? -9 : -10;
+    st = storage_view(bn ? k : n, bn ? n : k, rsb, csb, &vb);
+    if (st != 0) return st == 1 ? -13 : -14;
+    st = storage_view(m, n, rsc, csc, &vc);
+    if (st != 0) return st == 1 ? -18 : -19;
+    // an operand seen transposed flips its op
+    const char oa = va.transposed ? flip_op(transa) : transa;
+    const char ob = vb.transposed ? flip_op(transb) : transb;
+    if (!vc.transposed)
+        return run_decision(decide(oa, ob, m, n, k, alpha, A, dta, va.ld, B, dtb, vb.ld, beta, C, dtc, vc.ld,
+                                   comp, va.rs, vb.rs, vc.rs),
+                            stream);
+    // C seen transposed: C^T := beta C^T + alpha op(B)^T op(A)^T
+    return run_decision(decide(flip_op(ob), flip_op(oa), n, m, k, alpha, B, dtb, vb.ld, A, dta, va.ld, beta, C,
+                               dtc, vc.ld, comp, vb.rs, va.rs, vc.rs),
+                        stream);
 }
 
 int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_scalar alpha,

@@ -62,14 +62,14 @@ static void launch_v(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 }
 
 // The fast kernels take the operands' orientation (A contiguous along m for
-// 'N', B contiguous along n for 'T'/'C') as template parameters, and a ragged
+// 'N'/'R', B contiguous along n for 'T'/'C') as template parameters, and a ragged
 // variant for operands stored along k whose columns end inside a chunk (never
 // the case when both are stored along m/n); the generic kernels read the
 // orientation from the arguments.
 template <int CS>
 static void launch_c(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     if (a.a_vec && a.b_vec) {
-        const bool am = a.ta == 0, bm = a.tb != 0, rag = a.a_ragged || a.b_ragged;
+        const bool am = a.ta == 0 || a.ta == 3, bm = a.tb == 1 || a.tb == 2, rag = a.a_ragged || a.b_ragged;
         if (am) {
             if (bm) launch_v<CS, true, true, true, false>(a, s, nwg);
             else if (rag) launch_v<CS, true, true, false, true>(a, s, nwg);

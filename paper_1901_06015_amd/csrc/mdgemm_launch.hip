@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = t % g.m, j = t / g.m;
-        const int64_t off = i + j * g.ldc;
+        const int64_t off = i * g.rsc + j * g.ldc;
         if (g.c_cplx) {
             if (g.c_dbl) {
                 double *c = (double *)g.C + 2 * off;

@@ -35,8 +35,8 @@ def run(tc, ta, tb, m, n, k, comp="d", transa="N", transb="N", alpha=1.5, beta=-
         dist="uniform", seed=7, pad_a=0, pad_b=0, pad_c=0, stream=None):
     """Run one product on the GPU.  Returns (gpu result (m,n) complex128,
     host C after, host inputs dict)."""
-    ar, ac = (m, k) if transa.upper() == "N" else (k, m)
-    br, bc = (k, n) if transb.upper() == "N" else (n, k)
+    ar, ac = (m, k) if transa.upper() in "NR" else (k, m)
+    br, bc = (k, n) if transb.upper() in "NR" else (n, k)
     A = inputs.matrix(ar, ac, ta, seed * 3 + 1, ld=max(1, ar) + pad_a, dist=dist, pad=SENTINEL)
     B = inputs.matrix(br, bc, tb, seed * 3 + 2, ld=max(1, br) + pad_b, dist=dist, pad=SENTINEL)
     C = inputs.matrix(m, n, tc, seed * 3 + 3, ld=max(1, m) + pad_c, dist=dist, pad=SENTINEL)
@@ -47,6 +47,67 @@ def run(tc, ta, tb, m, n, k, comp="d", transa="N", transb="N", alpha=1.5, beta=-
     torch.cuda.synchronize()
     Cout = dC.cpu().numpy()
     return st, Cout, dict(A=A, B=B, C=C)
+
+
+def strided_store(X, rows, cols, rs, cs, pad=SENTINEL):
+    """A flat host buffer holding the rows x cols block of X at r*rs + c*cs;
+    every other element holds `pad`."""
+    size = (rows - 1) * rs + (cols - 1) * cs + 1 if rows and cols else 1
+    buf = np.full(size, pad, dtype=X.dtype)
+    if rows and cols:
+        r, c = np.meshgrid(np.arange(rows), np.arange(cols), indexing="ij")
+        buf[r * rs + c * cs] = X[:rows, :cols]
+    return buf
+
+
+def strides_of(layout, rows, cols, pad):
+    """(row stride, column stride) of a rows x cols operand stored by columns
+    ("col") or by rows ("row") with `pad` spare elements per column/row, or in
+    general storage with its columns ("gen", element stride 2) or its rows
+    ("genr", element stride 3) apart."""
+    if layout == "col":
+        return 1, max(1, rows) + pad
+    if layout == "row":
+        return max(1, cols) + pad, 1
+    if layout == "gen":
+        return 2, 2 * max(1, rows) + pad
+    return 3 * max(1, cols) + pad, 3
+
+
+def run_strided(tc, ta, tb, m, n, k, layouts, comp="d", transa="N", transb="N", alpha=1.5, beta=-0.5,
+                pads=(0, 0, 0), seed=7):
+    """One product through mdgemm_strided with each operand stored by rows or
+    by columns (layouts = (A, B, C) in "col"/"row").  Returns (status, gpu C
+    (m, n), padding-intact flag, reference, bound factors)."""
+    ar, ac = (m, k) if transa.upper() in "NR" else (k, m)
+    br, bc = (k, n) if transb.upper() in "NR" else (n, k)
+    shapes = ((ar, ac, ta), (br, bc, tb), (m, n, tc))
+    host, dev, st_ = [], [], []
+    for i, ((r, c, dt), lay, pad) in enumerate(zip(shapes, layouts, pads)):
+        X = inputs.matrix(r, c, dt, seed * 3 + 1 + i)
+        rs, cs = strides_of(lay, r, c, pad)
+        buf = strided_store(X, r, c, rs, cs)
+        host.append(buf)
+        st_.append((rs, cs))
+        dev.append(torch.from_numpy(buf).to("cuda"))
+    (rsa, csa), (rsb, csb), (rsc, csc) = st_
+    st = _lib.mdgemm_strided(transa, transb, m, n, k, alpha, dev[0].data_ptr(), ta, rsa, csa,
+                             dev[1].data_ptr(), tb, rsb, csb, beta, dev[2].data_ptr(), tc, rsc, csc, comp,
+                             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    cout = dev[2].cpu().numpy()
+    got = np.zeros((m, n), dtype=np.complex128)
+    mask = np.ones(cout.size, dtype=bool)
+    if m and n:
+        r, c = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+        got = cout[r * rsc + c * csc].astype(np.complex128)
+        mask[(r * rsc + c * csc).ravel()] = False
+    pad_ok = bool(np.all(cout[mask] == SENTINEL))
+    o = oracle.get()
+    sr, ref, g = o.gemm_gs(transa, transb, m, n, k, alpha, host[0], ta, rsa, csa, host[1], tb, rsb, csb,
+                           beta, host[2], tc, rsc, csc)
+    assert sr == 0, sr
+    return st, got, pad_ok, ref, g
 
 
 def reference(tc, ta, tb, m, n, k, ops, transa="N", transb="N", alpha=1.5, beta=-0.5):

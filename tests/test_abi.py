@@ -40,8 +40,8 @@ def test_version_and_strerror():
 
 def _plan(tc, ta, tb, comp=None, m=64, n=48, k=32, alpha=1.0, beta=0.0, transa="N", transb="N",
           lda=None, ldb=None, ldc=None, ptr=0x1000):
-    lda = lda or max(1, m if transa == "N" else k)
-    ldb = ldb or max(1, k if transb == "N" else n)
+    lda = lda or max(1, m if transa in "NRnr" else k)
+    ldb = ldb or max(1, k if transb in "NRnr" else n)
     ldc = ldc or max(1, m)
     return _lib.mdgemm_plan(transa, transb, m, n, k, alpha, ptr, ta, lda, ptr, tb, ldb, beta,
                             ptr, tc, ldc, comp)
@@ -123,6 +123,66 @@ def test_argument_errors():
     # A and B are not needed when alpha == 0 or k == 0
     assert call(A=None, B=None, alpha=0.0) == 0
     assert call(A=None, B=None, k=0) == 0
+
+
+def test_conjugate_without_transpose_plans_like_n():
+    """'R' (Section 2) reads A or B as stored, like 'N': same shapes, same
+    leading-dimension rule, same kernel family."""
+    for tc, ta, tb in (("z", "c", "z"), ("c", "z", "s"), ("d", "d", "d")):
+        stn, pn = _plan(tc, ta, tb, transa="N", transb="N")
+        str_, pr = _plan(tc, ta, tb, transa="R", transb="r")
+        assert stn == str_ == 0
+        assert (pn["case"], pn["flops"], pn["workgroups"]) == (pr["case"], pr["flops"], pr["workgroups"])
+    # lda counts rows of A as stored: m for 'R'
+    assert _plan("z", "c", "z", transa="R", lda=63)[0] == -9
+
+
+def test_strided_argument_errors():
+    """mdgemm_strided validates before touching the device: strides that make
+    an operand's elements overlap name their position."""
+    P = 0x1000
+    ok = dict(transa="N", transb="N", m=4, n=3, k=2, alpha=1.0, A=P, dta="d", rsa=1, csa=4, B=P, dtb="z",
+              rsb=1, csb=2, beta=0.0, C=P, dtc="c", rsc=1, csc=4, comp=None)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return _lib.mdgemm_strided(a["transa"], a["transb"], a["m"], a["n"], a["k"], a["alpha"],
+                                   a["A"], a["dta"], a["rsa"], a["csa"], a["B"], a["dtb"], a["rsb"], a["csb"],
+                                   a["beta"], a["C"], a["dtc"], a["rsc"], a["csc"], a["comp"], None)
+
+    assert call(transa="X") == -1
+    assert call(transb="?") == -2
+    assert call(m=-1) == -3
+    assert call(n=-1) == -4
+    assert call(k=-1) == -5
+    assert call(A=None) == -7
+    assert call(dta=9) == -8
+    assert call(rsa=0) == -9
+    assert call(csa=0) == -10
+    assert call(csa=3) == -10          # columns of a 4-row A overlap
+    assert call(rsa=1, csa=1) == -10
+    assert call(rsa=1, csa=-4) == -10
+    assert call(rsa=1, csa=1, transa="T") == -10   # A stored 2 x 4: columns overlap
+    assert call(rsa=3, csa=1, transa="T") == -9    # A stored 2 x 4 by rows: rows overlap below 4
+    assert call(B=None) == -11
+    assert call(dtb=5) == -12
+    assert call(rsb=0) == -13
+    assert call(csb=1) == -14
+    assert call(rsb=2, csb=1) == -13   # B stored by rows: 3 columns need a row stride >= 3
+    assert call(C=None) == -16
+    assert call(dtc=-1) == -17
+    assert call(rsc=0) == -18
+    assert call(csc=2) == -19
+    assert call(rsc=2, csc=1) == -18
+    assert call(comp=7) == -20
+    # general storage (neither stride 1): the elements must not overlap, so
+    # either the columns (cs >= rs*rows) or the rows (rs >= cs*cols) lie apart
+    assert call(rsa=2, csa=7) == -10   # 4 x 2: columns of span 8 overlap at 7
+    assert call(rsa=3, csa=2) == -9    # rows of span 4 overlap at 3
+    assert call(rsb=3, csb=5) == -14   # 2 x 3
+    assert call(rsc=5, csc=19) == -19  # 4 x 3
+    assert call(rsc=5, csc=20, C=None) == -16
 
 
 def test_grouped_empty_is_noop():

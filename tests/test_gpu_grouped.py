@@ -41,7 +41,7 @@ def make_entries(count, seed, lo=1, hi=300, dist="uniform", comps=("s", "d", "bf
         m, n, k = (int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi + 1))))) for _ in range(3))
         if comp == "bf16x3" and dist != "int":
             k = max(k, 96)  # the split's error fits the single-precision bound from k ~ 96 on
-        transa, transb = "NTC"[int(rng.integers(0, 3))], "NTC"[int(rng.integers(0, 3))]
+        transa, transb = "NTCR"[int(rng.integers(0, 4))], "NTCR"[int(rng.integers(0, 4))]
         case = oracle.get().case(tc, ta, tb)
         alpha = 0.75 - 0.5j if case == "3" else 1.5
         beta = (-0.5, 1.0, 0.0)[int(rng.integers(0, 3))]
@@ -53,8 +53,8 @@ def make_entries(count, seed, lo=1, hi=300, dist="uniform", comps=("s", "d", "bf
 def run_grouped(entries, dist="uniform"):
     descs, keep = [], []
     for e in entries:
-        ar, ac = (e["m"], e["k"]) if e["transa"] == "N" else (e["k"], e["m"])
-        br, bc = (e["k"], e["n"]) if e["transb"] == "N" else (e["n"], e["k"])
+        ar, ac = (e["m"], e["k"]) if e["transa"] in "NR" else (e["k"], e["m"])
+        br, bc = (e["k"], e["n"]) if e["transb"] in "NR" else (e["n"], e["k"])
         A = inputs.matrix(ar, ac, e["ta"], e["seed"] * 3 + 1, dist=dist)
         B = inputs.matrix(br, bc, e["tb"], e["seed"] * 3 + 2, dist=dist)
         C = inputs.matrix(e["m"], e["n"], e["tc"], e["seed"] * 3 + 3, ld=max(1, e["m"]) + 2, dist=dist,
@@ -163,8 +163,8 @@ def test_grouped_huge_leading_dimension_runs_alongside():
     o = oracle.get()
     descs, keep = [], []
     for idx, e in enumerate(entries):
-        ar, ac = (e["m"], e["k"]) if e["transa"] == "N" else (e["k"], e["m"])
-        br, bc = (e["k"], e["n"]) if e["transb"] == "N" else (e["n"], e["k"])
+        ar, ac = (e["m"], e["k"]) if e["transa"] in "NR" else (e["k"], e["m"])
+        br, bc = (e["k"], e["n"]) if e["transb"] in "NR" else (e["n"], e["k"])
         lda = (1 << 20) + 8 if idx == 2 else ar
         A = inputs.matrix(ar, ac, e["ta"], e["seed"] * 3 + 1, ld=lda)
         B = inputs.matrix(br, bc, e["tb"], e["seed"] * 3 + 2)

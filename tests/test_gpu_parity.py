@@ -12,7 +12,7 @@ import torch
 
 import gpu_util as gu
 import oracle
-from paper_1901_06015_amd import _lib
+from paper_1901_06015_amd import _lib, api, inputs
 
 pytestmark = pytest.mark.gpu
 TAGS = ("s", "d", "c", "z")
@@ -51,10 +51,11 @@ def test_all_storage_combinations(tc, comp):
         one(tc, ta, tb, 150, 140, 70, comp)
 
 
-@pytest.mark.parametrize("transa,transb", list(itertools.product("NTC", "NTC")))
+@pytest.mark.parametrize("transa,transb", list(itertools.product("NTCR", "NTCR")))
 def test_transpose_variants(transa, transb):
-    """The nine op(A), op(B) combinations of Section 1, on a combination of
-    every domain case."""
+    """The nine op(A), op(B) combinations of Section 1 plus conjugation
+    without transposition (R, Section 2), on a combination of every domain
+    case."""
     combos = ["ddd", "sdc", "dzs", "scz", "csd", "zdz", "czs", "zcz"]
     for i, cab in enumerate(combos):
         comp = "sd"[i % 2]
@@ -207,6 +208,86 @@ def test_bf16x3_transposes_and_loguniform():
             one(cab[0], cab[1], cab[2], 131, 97, 160, "bf16x3", transa, transb)
     for cab in ("sss", "css", "ccs", "ccc"):
         one(cab[0], cab[1], cab[2], 128, 128, 256, "bf16x3", dist="loguniform", beta=0.0)
+
+
+@pytest.mark.parametrize("layouts", list(itertools.product(("col", "row", "gen", "genr"), repeat=3)))
+def test_row_and_column_strides(layouts):
+    """Section 2's row and column strides: every operand stored by columns, by
+    rows (with spare elements between columns/rows) or in general storage
+    (neither stride 1), on a combination of every domain case and all four
+    ops; elements outside C's block are never written."""
+    combos = ["ddd", "sdc", "dzs", "scz", "csd", "zdz", "czs", "zcz"]
+    for i, cab in enumerate(combos):
+        comp = "sd"[i % 2]
+        transa, transb = "NTCR"[i % 4], "RCTN"[(i // 2) % 4]
+        for m, n, k, pads in ((77, 93, 41, (0, 0, 0)), (130, 66, 35, (3, 1, 2))):
+            say("strided %s%s%s comp=%s %s%s %s m=%d n=%d k=%d pads=%r" % (
+                cab[0], cab[1], cab[2], comp, transa, transb, "/".join(layouts), m, n, k, pads))
+            st, got, pad_ok, ref, g = gu.run_strided(cab[0], cab[1], cab[2], m, n, k, layouts, comp,
+                                                     transa, transb, pads=pads, seed=31 + i)
+            assert st == 0, (st, _lib.strerror(st))
+            gu.check(cab[0], comp, k, got, m, n, ref, g, what="strided %s %s%s %s" % (
+                cab, transa, transb, "/".join(layouts)))
+            assert pad_ok, "elements outside C's block were written"
+
+
+def test_row_major_torch_tensors():
+    """api.gemm on torch's default (row-major) tensors, mixed with
+    column-major ones, against the oracle given the same strides."""
+    o = oracle.get()
+    for i, (tc, ta, tb, transa, transb, comp) in enumerate((
+            ("z", "c", "d", "N", "N", "d"), ("s", "d", "z", "T", "R", "s"),
+            ("c", "z", "c", "R", "C", "s"), ("d", "d", "d", "N", "T", "d"))):
+        m, n, k = 150, 70, 99
+        say("api.gemm row-major %s%s%s %s%s comp=%s" % (tc, ta, tb, transa, transb, comp))
+        ash = (m, k) if transa in "NR" else (k, m)
+        bsh = (k, n) if transb in "NR" else (n, k)
+        XA = np.ascontiguousarray(inputs.matrix(ash[0], ash[1], ta, 50 + 3 * i))
+        XB = inputs.matrix(bsh[0], bsh[1], tb, 51 + 3 * i)
+        XC = np.ascontiguousarray(inputs.matrix(m, n, tc, 52 + 3 * i))
+        A = torch.from_numpy(XA).cuda()                            # stored by rows
+        B = torch.from_numpy(np.ascontiguousarray(XB.T)).cuda().t()  # stored by columns
+        C = torch.from_numpy(XC).cuda()                            # stored by rows
+        assert A.stride() == (k if transa in "NR" else m, 1) and B.stride(0) == 1 and C.stride() == (n, 1)
+        api.gemm(A, B, C, alpha=1.5, beta=-0.5, transa=transa, transb=transb, comp=comp)
+        torch.cuda.synchronize()
+        st, ref, g = o.gemm_gs(transa, transb, m, n, k, 1.5, XA.ravel(), ta, ash[1], 1,
+                               np.ascontiguousarray(XB.T).ravel(), tb, 1, bsh[0],
+                               -0.5, XC.ravel(), tc, n, 1)
+        assert st == 0
+        gu.check(tc, comp, k, C.cpu().numpy(), m, n, ref, g, what="api row-major %s%s%s" % (tc, ta, tb))
+
+
+def test_sliced_torch_tensors():
+    """api.gemm on strided slices (general storage: neither stride 1) of
+    larger tensors, against the oracle on the same host buffers."""
+    o = oracle.get()
+    m, n, k = 90, 70, 50
+    for i, (tc, ta, tb, transa, transb, comp) in enumerate((("z", "c", "d", "N", "T", "d"),
+                                                            ("c", "s", "z", "R", "N", "s"))):
+        say("api.gemm slices %s%s%s %s%s comp=%s" % (tc, ta, tb, transa, transb, comp))
+        ash = (m, k) if transa in "NR" else (k, m)
+        bsh = (k, n) if transb in "NR" else (n, k)
+        bigs = [np.ascontiguousarray(inputs.matrix(2 * r + 1, 3 * c + 2, dt, 60 + 3 * i + j))
+                for j, ((r, c), dt) in enumerate(((ash, ta), (bsh, tb), ((m, n), tc)))]
+        dev = [torch.from_numpy(b).cuda() for b in bigs]
+        A, B, C = (d[1::2, 2::3] for d in dev)
+        assert A.shape == ash and B.shape == bsh and C.shape == (m, n)
+        assert min(A.stride()) > 1 and min(C.stride()) > 1
+        refs = []
+        for t, b in zip((A, B, C), bigs):
+            refs.append((b.ravel()[t.storage_offset():], t.stride(0), t.stride(1)))
+        st, ref, g = o.gemm_gs(transa, transb, m, n, k, 1.5, refs[0][0], ta, refs[0][1], refs[0][2],
+                               refs[1][0], tb, refs[1][1], refs[1][2], -0.5, refs[2][0], tc, refs[2][1], refs[2][2])
+        assert st == 0
+        api.gemm(A, B, C, alpha=1.5, beta=-0.5, transa=transa, transb=transb, comp=comp)
+        torch.cuda.synchronize()
+        gu.check(tc, comp, k, C.cpu().numpy(), m, n, ref, g, what="slices %s%s%s" % (tc, ta, tb))
+        # the elements between the slices are untouched
+        out = dev[2].cpu().numpy()
+        keep = np.ones(out.shape, dtype=bool)
+        keep[1::2, 2::3] = False
+        assert np.array_equal(out[keep], bigs[2][keep])
 
 
 def test_huge_leading_dimension_generic_path():

@@ -43,9 +43,9 @@ def make_requests(srv, count, seed, hi=400, big_every=8):
             m, n, k = (int(np.floor(np.exp(rng.uniform(np.log(8), np.log(hi))))) for _ in range(3))
         if comp == "bf16x3":
             k = max(k, 96)
-        transa, transb = "NT"[int(rng.integers(0, 2))], "NC"[int(rng.integers(0, 2))]
-        ar, ac = (m, k) if transa == "N" else (k, m)
-        br, bc = (k, n) if transb == "N" else (n, k)
+        transa, transb = "NTR"[int(rng.integers(0, 3))], "NCR"[int(rng.integers(0, 3))]
+        ar, ac = (m, k) if transa in "NR" else (k, m)
+        br, bc = (k, n) if transb in "NR" else (n, k)
         A = inputs.matrix(ar, ac, ta, 9 * i + seed)
         B = inputs.matrix(br, bc, tb, 9 * i + seed + 1)
         C = inputs.matrix(m, n, tc, 9 * i + seed + 2)
