@@ -52,6 +52,8 @@ class Oracle:
         common = [cc, cc, i64, i64, i64, dbl, dbl, vp, ci, i64, vp, ci, i64, dbl, dbl, vp, ci, i64]
         lib.md_oracle_gemm.argtypes = common + [vp, vp]
         lib.md_oracle_gemm.restype = ci
+        lib.md_oracle_gemm_literal.argtypes = common + [vp, vp]
+        lib.md_oracle_gemm_literal.restype = ci
         lib.md_oracle_gemm_at.argtypes = common + [i64, vp, vp, vp, vp]
         lib.md_oracle_gemm_at.restype = ci
         lib.md_oracle_gemm_gs.argtypes = [cc, cc, i64, i64, i64, dbl, dbl, vp, ci, i64, i64, vp, ci, i64, i64,
@@ -87,11 +89,14 @@ class Oracle:
                 beta.real, beta.imag, ptr(C), tag(dtc), ldc)
 
     def gemm(self, transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb,
-             beta, C, dtc, ldc, want_bound=True):
-        """Full reference.  Returns (status, cref complex128 (m, n), g float64 (m, n))."""
+             beta, C, dtc, ldc, want_bound=True, literal_alpha=False):
+        """Full reference.  Returns (status, cref complex128 (m, n), g float64 (m, n)).
+        literal_alpha: apply a complex alpha as given in every case (the literal
+        interpretation of Section 6.2) instead of refusing it in the mixed cases."""
         cref = np.zeros((max(m, 0), max(n, 0)), dtype=np.complex128, order="F")
         g = np.zeros((max(m, 0), max(n, 0)), dtype=np.float64, order="F") if want_bound else None
-        st = self.lib.md_oracle_gemm(*self._args(transa, transb, m, n, k, alpha, A, dta, lda,
+        fn = self.lib.md_oracle_gemm_literal if literal_alpha else self.lib.md_oracle_gemm
+        st = fn(*self._args(transa, transb, m, n, k, alpha, A, dta, lda,
                                                  B, dtb, ldb, beta, C, dtc, ldc),
                                      cref.ctypes.data, g.ctypes.data if g is not None else None)
         return st, cref, g

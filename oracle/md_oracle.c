@@ -16,9 +16,11 @@
  *      complex product written out in real arithmetic;
  *   4. the scalars follow Section 6: alpha is used as given (a complex alpha
  *      with a non-zero imaginary part is refused in the six mixed cases of
- *      Section 6.2; in case 0 the product is real so Re(alpha*AB) equals
- *      Re(alpha)*AB, the projection the paper describes); beta is reduced to
- *      Re(beta) when C is real (Section 6.2);
+ *      Section 6.2, except by md_oracle_gemm_literal, which computes those
+ *      cases under the literal interpretation Section 6.2 describes, all
+ *      five operands taken in their own domains; in case 0 the product is
+ *      real so Re(alpha*AB) equals Re(alpha)*AB, the projection the paper
+ *      describes); beta is reduced to Re(beta) when C is real (Section 6.2);
  *   5. a real C keeps Re of the result.  Figure "mixeddom"'s interpretations
  *      (A Re(B), Re(A) B, Re(AB), AB into Re(C), complex products with an
  *      implicit zero imaginary part) are all what steps 1-5 give.
@@ -165,18 +167,18 @@ static void entry(char ta, char tb, int64_t k,
     if (out_g) *out_g = g;
 }
 
-int md_oracle_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
-                   double alpha_re, double alpha_im,
-                   const void *A, int dta, int64_t lda,
-                   const void *B, int dtb, int64_t ldb,
-                   double beta_re, double beta_im,
-                   const void *C, int dtc, int64_t ldc,
-                   double *cref, double *g)
+static int gemm_colmajor(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                         double alpha_re, double alpha_im,
+                         const void *A, int dta, int64_t lda,
+                         const void *B, int dtb, int64_t ldb,
+                         double beta_re, double beta_im,
+                         const void *C, int dtc, int64_t ldc,
+                         double *cref, double *g, int literal)
 {
     char ta = norm_trans(transa), tb = norm_trans(transb);
     int st = check_args(ta, tb, m, n, k, dta, lda, dtb, ldb, dtc, ldc);
     if (st != ORACLE_OK) return st;
-    if (alpha_refused(dtc, dta, dtb, alpha_im)) return ORACLE_ERR_ALPHA_IMAG;
+    if (!literal && alpha_refused(dtc, dta, dtb, alpha_im)) return ORACLE_ERR_ALPHA_IMAG;
     for (int64_t j = 0; j < n; ++j) {
         for (int64_t i = 0; i < m; ++i) {
             int64_t o = i + j * m;
@@ -186,6 +188,30 @@ int md_oracle_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
         }
     }
     return ORACLE_OK;
+}
+
+int md_oracle_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                   double alpha_re, double alpha_im,
+                   const void *A, int dta, int64_t lda,
+                   const void *B, int dtb, int64_t ldb,
+                   double beta_re, double beta_im,
+                   const void *C, int dtc, int64_t ldc,
+                   double *cref, double *g)
+{
+    return gemm_colmajor(transa, transb, m, n, k, alpha_re, alpha_im, A, dta, lda, B, dtb, ldb,
+                         beta_re, beta_im, C, dtc, ldc, cref, g, 0);
+}
+
+int md_oracle_gemm_literal(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                           double alpha_re, double alpha_im,
+                           const void *A, int dta, int64_t lda,
+                           const void *B, int dtb, int64_t ldb,
+                           double beta_re, double beta_im,
+                           const void *C, int dtc, int64_t ldc,
+                           double *cref, double *g)
+{
+    return gemm_colmajor(transa, transb, m, n, k, alpha_re, alpha_im, A, dta, lda, B, dtb, ldb,
+                         beta_re, beta_im, C, dtc, ldc, cref, g, 1);
 }
 
 int md_oracle_gemm_at(char transa, char transb, int64_t m, int64_t n, int64_t k,

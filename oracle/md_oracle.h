@@ -53,6 +53,17 @@ int md_oracle_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                    const void *C, int dtc, int64_t ldc,
                    double *cref, double *g);
 
+/* The same under the literal interpretation of Section 6.2: a complex alpha
+ * is applied as given in every case, so the six mixed cases accept
+ * Im(alpha) != 0 (never returns ORACLE_ERR_ALPHA_IMAG). */
+int md_oracle_gemm_literal(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                           double alpha_re, double alpha_im,
+                           const void *A, int dta, int64_t lda,
+                           const void *B, int dtb, int64_t ldb,
+                           double beta_re, double beta_im,
+                           const void *C, int dtc, int64_t ldc,
+                           double *cref, double *g);
+
 /* The same definition evaluated only at `count` entries (rows[t], cols[t]);
  * cref has 2*count doubles, g (optional) count doubles. */
 int md_oracle_gemm_at(char transa, char transb, int64_t m, int64_t n, int64_t k,

@@ -434,9 +434,51 @@ def pin_strides(o):
     return fails
 
 
+def pin_literal_alpha(o):
+    """Section 6.2's literal interpretation (all five operands in their own
+    domains): with Im(alpha) != 0 every one of the 64 storage combinations
+    equals the homogeneous complex product alpha*op(A)*op(B) + beta*C formed by
+    numpy, projected to Re for a real C -- exactly for integer inputs; and for
+    a real alpha it equals the paper's policy result bit for bit."""
+    fails = []
+    alpha, beta = 0.75 - 0.5j, -0.5 + 0.25j
+    m, n, k = 5, 4, 6
+    for i, (tc, ta_, tb_) in enumerate(itertools.product(("s", "d", "c", "z"), repeat=3)):
+        trans = ("N", "T", "C", "R")
+        ta, tb = trans[i % 4], trans[(i // 4) % 4]
+        for dist in ("int", "uniform"):
+            A, B, C, ar, br = _operands(ta_, tb_, tc, m, n, k, ta, tb, seed=300 + i, dist=dist)
+            st, got, _ = o.gemm(ta, tb, m, n, k, alpha, A, ta_, A.shape[0], B, tb_, B.shape[0], beta, C, tc,
+                                C.shape[0], literal_alpha=True)
+            if st != 0:
+                fails.append("literal %s%s%s status %d" % (tc, ta_, tb_, st))
+                continue
+            ac = (m, k) if ta in "NR" else (k, m)
+            bc = (k, n) if tb in "NR" else (n, k)
+            X = _op(A, ac[0], ac[1], ta) @ _op(B, bc[0], bc[1], tb)
+            be = beta if tc in "cz" else beta.real
+            want = alpha * X + be * np.asarray(C[:m, :n], dtype=np.complex128)
+            if tc in "sd":
+                want = want.real.astype(np.complex128)
+            if dist == "int":
+                ok = np.array_equal(got, want)
+            else:
+                ok = np.allclose(got, want, rtol=0, atol=1e-12)
+            if not ok:
+                fails.append("literal %s%s%s %s%s (%s) differs from numpy by %.3g" % (
+                    tc, ta_, tb_, ta, tb, dist, float(np.max(np.abs(got - want)))))
+            st1, r1, _ = o.gemm(ta, tb, m, n, k, 1.25, A, ta_, A.shape[0], B, tb_, B.shape[0], beta, C, tc,
+                                C.shape[0], literal_alpha=True)
+            st2, r2, _ = o.gemm(ta, tb, m, n, k, 1.25, A, ta_, A.shape[0], B, tb_, B.shape[0], beta, C, tc,
+                                C.shape[0])
+            if not (st1 == st2 == 0 and np.array_equal(r1, r2)):
+                fails.append("literal %s%s%s with a real alpha differs from the policy result" % (tc, ta_, tb_))
+    return fails
+
+
 ALL_PINS = (pin_case_table, pin_flops, pin_same_type, pin_domain_identities,
             pin_exact_integers, pin_exact_rational, pin_1m_equations, pin_scalars,
-            pin_transpose, pin_strides)
+            pin_transpose, pin_strides, pin_literal_alpha)
 
 
 def run_all(o):

@@ -1,8 +1,8 @@
 """Plausible mistakes planted in copies of the oracle (on the CPU) must each be
 caught by at least one pin.  This shows the pins constrain every part of the
 definition: sign and index of each term, transposition, conjugation (with and
-without transposition), the strides, the scalar policies and the real-C
-projection."""
+without transposition), the strides, the scalar policies (including the
+literal interpretation of a complex alpha) and the real-C projection."""
 import os
 import shutil
 
@@ -35,6 +35,10 @@ MUTANTS = {
     "single_promoted_wrong": ("*im = (double)((const float *)X)[2 * idx + 1];",
                               "*im = (double)((const float *)X)[2 * idx];"),
     "last_k_dropped": ("for (int64_t p = 0; p < k; ++p) {", "for (int64_t p = 0; p + 1 < k; ++p) {"),
+    "literal_still_refuses": ("if (!literal && alpha_refused(dtc, dta, dtb, alpha_im))",
+                              "if (alpha_refused(dtc, dta, dtb, alpha_im))"),
+    "alpha_projected_in_mixed_cases": ("if (md_oracle_case(dtc, dta, dtb) == 0)",
+                                       "if (md_oracle_case(dtc, dta, dtb) != 7)"),
     "flops_case2": ("double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 4.0 : 8.0);",
                     "double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 8.0 : 8.0);"),
 }
