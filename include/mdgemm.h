@@ -49,7 +49,17 @@ typedef enum {
     MD_COMP_DEFAULT = -1,
     MD_COMP_S = 0,
     MD_COMP_D = 1,
-    MD_COMP_S_BF16X3 = 2
+    MD_COMP_S_BF16X3 = 2,
+    /* Flag, OR'ed into MD_COMP_S, MD_COMP_D or MD_COMP_S_BF16X3 (not into
+     * MD_COMP_DEFAULT): a complex alpha is applied as given in the six mixed
+     * cases too, under the literal interpretation Section 6.2 describes (all
+     * five operands in their own domains), instead of being refused.  With C
+     * real (cases 1a, 1b, 2ab) alpha is folded into the complex operand as it
+     * is staged (Re(alpha*A), Re(alpha*B), alpha*A: the packing the paper
+     * suggests in a footnote to Section 6.2), so the flop count stays the
+     * case's minimum; with C complex (1c, 2ac, 2bc) the epilogue multiplies
+     * by the complex alpha.  An extension of the paper's policy. */
+    MD_COMP_LITERAL_ALPHA = 0x100
 } md_comp;
 
 /* alpha and beta are always passed as complex double; see Section 6 for how
@@ -87,7 +97,8 @@ typedef enum {
  *  (3) m, (4) n, (5) k     : op(A) is m x k, op(B) is k x n, C is m x n; >= 0.
  *  (6) alpha               : cast to the computation precision (Section 6.1,
  *        option 1).  Im(alpha) is ignored in case 0 and used in case 3; in the
- *        other six cases a non-zero Im(alpha) returns MD_ERR_ALPHA_IMAG.
+ *        other six cases a non-zero Im(alpha) returns MD_ERR_ALPHA_IMAG unless
+ *        comp carries MD_COMP_LITERAL_ALPHA.
  *  (7) A, (8) dta, (9) lda : operand A, its storage type, leading dimension.
  *  (10) B, (11) dtb, (12) ldb : operand B likewise.
  *  (13) beta               : cast to C's storage precision (Section 6.1,

@@ -91,8 +91,21 @@ def tag(dt):
     return DT_TAG[dt] if isinstance(dt, str) else int(dt)
 
 
+MD_COMP_LITERAL_ALPHA = 0x100
+
+
 def comp_tag(comp):
-    return COMP_TAG[comp] if (comp is None or isinstance(comp, str)) else int(comp)
+    """None/"default", "s", "d", "bf16x3", or one of the last three with
+    "+literal" (MD_COMP_LITERAL_ALPHA: a complex alpha applied as given in the
+    mixed cases), or an int passed through."""
+    if comp is None or not isinstance(comp, str):
+        return COMP_TAG[comp] if comp is None else int(comp)
+    if comp.endswith("+literal"):
+        base = comp[:-len("+literal")]
+        if base not in ("s", "d", "bf16x3"):
+            raise ValueError("the literal-alpha flag needs an explicit precision (s, d or bf16x3)")
+        return COMP_TAG[base] | MD_COMP_LITERAL_ALPHA
+    return COMP_TAG[comp]
 
 
 def _ch(t):

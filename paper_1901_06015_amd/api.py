@@ -80,11 +80,18 @@ def _strides(t, name):
     return t.data_ptr(), dt_of(t), rs, cs
 
 
-def gemm(A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", comp=None, stream=None):
+def gemm(A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", comp=None, stream=None,
+         literal_alpha=False):
     """C := beta*C + alpha*op(A)*op(B) on the GPU, enqueued on `stream` (default:
     torch's current stream for C's device).  Each tensor may be stored by rows
     or by columns.  `comp` is None (C's precision), "s", "d" or "bf16x3".
+    literal_alpha: apply a complex alpha as given in the mixed-domain cases
+    (the literal interpretation of Section 6.2) instead of refusing it.
     Returns C."""
+    if literal_alpha:
+        if comp is None:
+            comp = "d" if C.dtype in (torch.float64, torch.complex128) else "s"
+        comp = comp + "+literal"
     for t, nm in ((A, "A"), (B, "B"), (C, "C")):
         if not t.is_cuda:
             raise ValueError("%s must be a device tensor" % nm)

@@ -70,6 +70,8 @@ struct GemmArgs {
     int beta_zero;            // C is not read
     double alpha_re, alpha_im;
     double beta_re, beta_im;
+    int a_scale, b_scale;       // stage A (B) as (scale_re + i scale_im) times itself: a complex
+    double scale_re, scale_im;  // alpha under the literal interpretation with C real
     int tiles_m, tiles_n;     // workgroup tiles of the real product
 };
 

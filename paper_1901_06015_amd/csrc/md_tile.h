@@ -184,6 +184,11 @@ struct Stage {
     int64_t ld, rs, MN, K, mn0;  // rs: element stride along a stored column (generic path)
     int64_t total_bytes;  // extent of the stored matrix
     bool mn_contig, conj;
+    // Scaling by a complex alpha while staging (literal interpretation, real C):
+    // only the complex operand of cases 1a, 1b and 2ab is ever scaled.
+    static constexpr bool CAN_SCALE = (MODE == M_REONLY || MODE == M_KINT) && W == 2;
+    bool scl;
+    T sre, sim;
     int cpc_log;          // log2 of chunks per stored column inside a tile
     int pos, col0;        // this thread's chunk 0: position in its column, column in the tile
     int col_step;         // columns between a thread's consecutive chunks
@@ -194,6 +199,9 @@ struct Stage {
         // A is stored along m for 'N'/'R', B along n for 'T'/'C'
         mn_contig = FAST ? MNC : (IS_A ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2));
         conj = tr >= 2;
+        scl = CAN_SCALE && (IS_A ? g.a_scale : g.b_scale);
+        sre = (T)g.scale_re;
+        sim = (T)g.scale_im;
         ld = IS_A ? g.lda : g.ldb;
         rs = IS_A ? g.rsa : g.rsb;
         MN = IS_A ? g.m : g.n;
@@ -339,10 +347,49 @@ struct Stage {
         __device__ __forceinline__ void put(int kk, int mm, T v) const { lds[L::at(kk, mm)] = v; }
     };
 
+    // Position (mm, kk) of element e of chunk column col.
+    __device__ __forceinline__ void where(int e, int col, int *mm, int *kk) const {
+        if constexpr (FAST) {
+            *mm = MNC ? e : col;
+            *kk = MNC ? col : e;
+        } else {
+            *mm = mn_contig ? e : col;
+            *kk = mn_contig ? col : e;
+        }
+    }
+
+    // The scaled form of store_to: each complex element x (conjugated first
+    // for 'C'/'R') is placed as alpha*x, rounded in the computation type.
+    template <class Out>
+    __device__ __forceinline__ void store_scaled(Out out) const {
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            const int col = col0 + c * col_step;
+#pragma unroll
+            for (int q = 0; q < CW; q += 2) {
+                const T re = component(raw[c], q);
+                const T im0 = component(raw[c], q + 1);
+                const T im = conj ? -im0 : im0;
+                const T pr = fma(sre, re, -(sim * im));
+                const T pi = fma(sre, im, sim * re);
+                int mm, kk;
+                where(pos * (CW / W) + q / W, col, &mm, &kk);
+                emit(out, mm, kk, 0, pr, false);
+                emit(out, mm, kk, 1, pi, false);
+            }
+        }
+    }
+
     // Convert the staged registers and hand every element to `out`.
     template <class Out>
     __device__ __forceinline__ void store_to(Out out) const {
         if (PARTIAL && !active) return;
+        if constexpr (CAN_SCALE) {
+            if (scl) {
+                store_scaled(out);
+                return;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;

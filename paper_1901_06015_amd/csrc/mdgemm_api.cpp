@@ -22,6 +22,15 @@ int norm_trans(char t) {
 
 bool dt_ok(int dt) { return dt >= MD_S && dt <= MD_Z; }
 
+// A computation precision, optionally with MD_COMP_LITERAL_ALPHA OR'ed into an
+// explicit one.
+bool comp_ok(int comp) {
+    if (comp == MD_COMP_DEFAULT) return true;
+    if (comp < 0) return false;
+    const int base = comp & ~MD_COMP_LITERAL_ALPHA;
+    return base == MD_COMP_S || base == MD_COMP_D || base == MD_COMP_S_BF16X3;
+}
+
 // The op of an operand after swapping its row and column strides (its
 // transpose): N <-> T, R <-> C.
 char flip_op(char t) {
@@ -97,10 +106,9 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     if (m > 0 && n > 0 && C == nullptr) { d.status = -14; return d; }
     if (!dt_ok(dtc)) { d.status = -15; return d; }
     if (ldc / rsc < max1(m)) { d.status = -16; return d; }
-    if (comp != MD_COMP_DEFAULT && comp != MD_COMP_S && comp != MD_COMP_D && comp != MD_COMP_S_BF16X3) {
-        d.status = -17;
-        return d;
-    }
+    if (!comp_ok(comp)) { d.status = -17; return d; }
+    const bool literal = comp != MD_COMP_DEFAULT && (comp & MD_COMP_LITERAL_ALPHA);
+    if (literal) comp &= ~MD_COMP_LITERAL_ALPHA;
 
     // Section 4.1.1: the computation precision defaults to C's storage precision.
     if (comp == MD_COMP_DEFAULT) comp = dt_dbl(dtc) ? MD_COMP_D : MD_COMP_S;
@@ -108,10 +116,23 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     d.cs = classify(dtc, dta, dtb);
 
     // Section 6.2: Im(alpha) is projected away in case 0, used in case 3 and
-    // refused in the six mixed cases.
+    // refused in the six mixed cases -- unless the caller asks for the literal
+    // interpretation: then a complex C takes the complex alpha in the epilogue,
+    // and for a real C the complex operand is staged as alpha times itself
+    // (Re(alpha A) B, A Re(alpha B), Re((alpha A) B)) with the epilogue's alpha 1.
     double are = alpha.re, aim = alpha.im;
+    int a_scale = 0, b_scale = 0;
+    double sre = 0.0, sim = 0.0;
     if (d.cs == MD_CASE_0) aim = 0.0;
-    else if (d.cs != MD_CASE_3 && aim != 0.0) { d.status = MD_ERR_ALPHA_IMAG; return d; }
+    else if (d.cs != MD_CASE_3 && aim != 0.0) {
+        if (!literal) { d.status = MD_ERR_ALPHA_IMAG; return d; }
+        if (d.cs == MD_CASE_1A || d.cs == MD_CASE_1B || d.cs == MD_CASE_2AB) {
+            a_scale = d.cs != MD_CASE_1B;
+            b_scale = d.cs == MD_CASE_1B;
+            sre = are; sim = aim;
+            are = 1.0; aim = 0.0;
+        }
+    }
     // Section 6.2: Im(beta) cannot change a real C.
     double bre = beta.re, bim = dt_cplx(dtc) ? beta.im : 0.0;
     // Section 6.1 option (1): beta takes C's storage precision.
@@ -143,6 +164,8 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     g.a_ragged = (ta == 1 || ta == 2) && (k * wa) % cwa != 0;
     g.b_ragged = (tb == 0 || tb == 3) && (k * wb) % cwb != 0;
     g.alpha_re = are; g.alpha_im = aim;
+    g.a_scale = a_scale; g.b_scale = b_scale;
+    g.scale_re = sre; g.scale_im = sim;
     g.beta_re = bre; g.beta_im = bim;
     g.beta_zero = (bre == 0.0 && bim == 0.0);
 
@@ -211,7 +234,7 @@ int mdgemm_strided(char transa, char transb, int64_t m, int64_t n, int64_t k, md
     if (!dt_ok(dtb)) return -12;
     if (m > 0 && n > 0 && C == nullptr) return -16;
     if (!dt_ok(dtc)) return -17;
-    if (comp != MD_COMP_DEFAULT && comp != MD_COMP_S && comp != MD_COMP_D && comp != MD_COMP_S_BF16X3) return -20;
+    if (!comp_ok(comp)) return -20;
     // each operand as a column-major view: its stored block (rows x cols),
     // or its transpose when its rows lie apart
     const bool an = ta == 0 || ta == 3, bn = tb == 0 || tb == 3;

@@ -79,8 +79,11 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         if (d.status != MD_OK) return d.status;
         if (d.quick == 1) continue;
         // the grouped kernel addresses an operand tile with 32-bit offsets:
-        // 128 columns of 32 components of 16 bytes must span less than 2 GiB
-        if (d.quick == 0 && (x.lda >= ((int64_t)1 << 20) || x.ldb >= ((int64_t)1 << 20))) {
+        // 128 columns of 32 components of 16 bytes must span less than 2 GiB;
+        // it also does not scale an operand while staging it (a complex alpha
+        // under the literal interpretation with C real)
+        if (d.quick == 0 && (x.lda >= ((int64_t)1 << 20) || x.ldb >= ((int64_t)1 << 20) || d.g.a_scale ||
+                             d.g.b_scale)) {
             alone.push_back(i);
             continue;
         }

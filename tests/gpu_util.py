@@ -110,15 +110,16 @@ def run_strided(tc, ta, tb, m, n, k, layouts, comp="d", transa="N", transb="N", 
     return st, got, pad_ok, ref, g
 
 
-def reference(tc, ta, tb, m, n, k, ops, transa="N", transb="N", alpha=1.5, beta=-0.5):
+def reference(tc, ta, tb, m, n, k, ops, transa="N", transb="N", alpha=1.5, beta=-0.5, literal_alpha=False):
     A, B, C = ops["A"], ops["B"], ops["C"]
     st, ref, g = oracle.get().gemm(transa, transb, m, n, k, alpha, A, ta, A.shape[0],
-                                   B, tb, B.shape[0], beta, C, tc, C.shape[0])
+                                   B, tb, B.shape[0], beta, C, tc, C.shape[0], literal_alpha=literal_alpha)
     assert st == 0, st
     return ref, g
 
 
 def bound(tc, comp, k, ref, g, extra=0.0):
+    comp = comp.split("+")[0] if isinstance(comp, str) else comp  # "+literal" does not change the precision
     ux = U[comp if comp in ("s", "d") else ("s" if comp == "bf16x3" else PREC[tc])]
     uc = U[PREC[tc]]
     return 4.0 * k * ux * g + 4.0 * uc * np.abs(ref) + extra

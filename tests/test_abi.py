@@ -79,6 +79,22 @@ def test_alpha_policy():
             assert st == _lib.MD_ERR_ALPHA_IMAG
 
 
+def test_literal_alpha_flag():
+    """MD_COMP_LITERAL_ALPHA lifts Section 6.2's refusal of Im(alpha) in the
+    six mixed cases; it needs an explicit precision and changes no flop count."""
+    for tc, ta, tb in itertools.product(("s", "c"), ("d", "z"), ("s", "c")):
+        st0, p0 = _plan(tc, ta, tb, comp="d", alpha=1.0 + 0.5j)
+        st1, p1 = _plan(tc, ta, tb, comp="d+literal", alpha=1.0 + 0.5j)
+        assert st1 == 0, (tc, ta, tb, st1)
+        st2, p2 = _plan(tc, ta, tb, comp="d", alpha=1.0)
+        assert p1["flops"] == p2["flops"] and p1["kernel"] == p2["kernel"] and p1["comp"] == 1
+    assert _plan("s", "c", "s", comp="s+literal", alpha=2j)[1]["comp"] == 0
+    assert _plan("s", "c", "s", comp=_lib.MD_COMP_LITERAL_ALPHA | 7, alpha=2j)[0] == -17
+    assert _plan("s", "c", "s", comp=-2, alpha=1.0)[0] == -17
+    with pytest.raises(ValueError):
+        _lib.comp_tag("default+literal")
+
+
 def test_quick_returns():
     assert _plan("d", "d", "d", m=0)[1]["quick"] == 1
     assert _plan("d", "d", "d", n=0)[1]["quick"] == 1

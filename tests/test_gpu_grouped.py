@@ -73,7 +73,8 @@ def check_all(entries, keep, exact=False):
     o = oracle.get()
     for e, (A, B, C, dA, dB, dC) in zip(entries, keep):
         st, ref, g = o.gemm(e["transa"], e["transb"], e["m"], e["n"], e["k"], e["alpha"], A, e["ta"],
-                            A.shape[0], B, e["tb"], B.shape[0], e["beta"], C, e["tc"], C.shape[0])
+                            A.shape[0], B, e["tb"], B.shape[0], e["beta"], C, e["tc"], C.shape[0],
+                            literal_alpha="+literal" in str(e["comp"]))
         assert st == 0
         Cout = dC.cpu().numpy()
         what = "%s%s%s/%s %s%s %dx%dx%d" % (e["tc"], e["ta"], e["tb"], e["comp"], e["transa"], e["transb"],
@@ -100,6 +101,23 @@ def test_grouped_exact_inputs_bitwise():
     st, keep = run_grouped(entries, dist="int")
     assert st == 0
     check_all(entries, keep, exact=True)
+
+
+def test_grouped_literal_complex_alpha():
+    """A grouped call mixing literal complex alphas in all six mixed cases
+    (real-C cases run on the plain kernels inside the call, complex-C cases in
+    the grouped kernel) with ordinary products: each matches the oracle."""
+    entries = make_entries(40, seed=17)
+    o = oracle.get()
+    for i, e in enumerate(entries):
+        if o.case(e["tc"], e["ta"], e["tb"]) not in ("0", "3") and e["comp"] != "bf16x3" and i % 2 == 0:
+            e["alpha"] = 0.75 - 0.5j
+            e["comp"] = e["comp"] + "+literal"
+    assert sum("+literal" in e["comp"] for e in entries) >= 8
+    say("grouped literal alpha batch of", len(entries))
+    st, keep = run_grouped(entries)
+    assert st == 0, (st, _lib.strerror(st))
+    check_all(entries, keep)
 
 
 def test_grouped_every_combination_once():

@@ -290,6 +290,57 @@ def test_sliced_torch_tensors():
         assert np.array_equal(out[keep], bigs[2][keep])
 
 
+MIXED = {"1a": ("scs", "dcd", "szs"), "1b": ("ssc", "dsz", "sdc"), "1c": ("css", "zdd", "zsd"),
+         "2ab": ("scc", "dzc", "szz"), "2ac": ("ccs", "zcd", "czs"), "2bc": ("csc", "zdz", "cdc")}
+
+
+@pytest.mark.parametrize("case", sorted(MIXED))
+def test_literal_complex_alpha(case):
+    """MD_COMP_LITERAL_ALPHA: Im(alpha) != 0 in the six mixed cases, applied as
+    the literal interpretation of Section 6.2 (the oracle's literal variant),
+    in both precisions and BF16x3, with every op on both operands, on the fast
+    path, the ragged/unaligned path and the component-wise path."""
+    alpha, beta = 0.75 - 0.5j, -0.5 + 0.25j
+    for i, cab in enumerate(MIXED[case]):
+        for comp in ("s+literal", "d+literal", "bf16x3+literal"):
+            transa, transb = "NTCR"[i % 4], "CRNT"[(i + len(comp)) % 4]
+            for m, n, k, pads in ((150, 140, 112, (0, 0, 0)), (77, 93, 97, (1, 3, 2))):
+                say("literal alpha %s %s %s %s%s m=%d n=%d k=%d pads=%r" % (case, cab, comp, transa, transb,
+                                                                         m, n, k, pads))
+                st, Cout, ops = gu.run(cab[0], cab[1], cab[2], m, n, k, comp=comp, transa=transa, transb=transb,
+                                       alpha=alpha, beta=beta, seed=40 + i, pad_a=pads[0], pad_b=pads[1],
+                                       pad_c=pads[2])
+                assert st == 0, (st, _lib.strerror(st))
+                ref, g = gu.reference(cab[0], cab[1], cab[2], m, n, k, ops, transa, transb, alpha, beta,
+                                      literal_alpha=True)
+                gu.check(cab[0], comp, k, Cout, m, n, ref, g, what="literal %s %s %s" % (case, cab, comp))
+                gu.check_padding(Cout, m, "C")
+        # without the flag the paper's policy still refuses
+        st, _, _ = gu.run(cab[0], cab[1], cab[2], 8, 8, 8, comp="d", alpha=alpha, beta=beta)
+        assert st == _lib.MD_ERR_ALPHA_IMAG
+
+
+def test_literal_complex_alpha_exact_inputs_bitwise():
+    """Integer entries, alpha = 0.75 - 0.5i, beta = -0.5: the staged alpha*x and
+    every sum are exact, so all 48 mixed-case combinations equal the oracle's
+    literal result bit for bit."""
+    o = oracle.get()
+    for tc, ta, tb in itertools.product(TAGS, TAGS, TAGS):
+        if o.case(tc, ta, tb) in ("0", "3"):
+            continue
+        for comp in ("s+literal", "d+literal"):
+            say("literal exact %s%s%s %s" % (tc, ta, tb, comp))
+            m, n, k = 70, 66, 45
+            st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, dist="int", seed=13, alpha=0.75 - 0.5j,
+                                   transa="C" if ta in "cz" else "N")
+            assert st == 0
+            ref, _ = gu.reference(tc, ta, tb, m, n, k, ops, "C" if ta in "cz" else "N", "N", 0.75 - 0.5j,
+                                  literal_alpha=True)
+            got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+            assert np.array_equal(got, ref), "literal exact %s%s%s/%s: %d mismatches" % (
+                tc, ta, tb, comp, int((got != ref).sum()))
+
+
 def test_huge_leading_dimension_generic_path():
     """A leading dimension of 2^20 or more keeps the kernels' 32-bit tile
     offsets from fitting: the component-wise path takes over, with the same
