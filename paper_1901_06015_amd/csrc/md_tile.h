@@ -151,7 +151,9 @@ __device__ __forceinline__ int split_pos(int mm, int q) { return (((mm >> 4) << 
 //       LDS layout is [k][mn] (MNC must be true).
 // RAG (fast path only): the operand's columns may end inside a chunk; an
 // operand stored contiguous along k then masks what a chunk reads past them.
-template <class T, int CS, bool IS_A, bool FAST, bool SDBL, bool MNC, class C = TileCfg<T>, bool RAG = false>
+// SCL: the operand is staged as (scale_re + i scale_im) times itself.
+template <class T, int CS, bool IS_A, bool FAST, bool SDBL, bool MNC, class C = TileCfg<T>, bool RAG = false,
+          bool SCL = false>
 struct Stage {
     static constexpr int MODE = mode_of<CS, IS_A>();
     static constexpr int W = (MODE == M_PLAIN) ? 1 : 2;  // stored components per element
@@ -185,9 +187,9 @@ struct Stage {
     int64_t total_bytes;  // extent of the stored matrix
     bool mn_contig, conj;
     // Scaling by a complex alpha while staging (literal interpretation, real C):
-    // only the complex operand of cases 1a, 1b and 2ab is ever scaled.
-    static constexpr bool CAN_SCALE = (MODE == M_REONLY || MODE == M_KINT) && W == 2;
-    bool scl;
+    // only the complex operand of cases 1a, 1b and 2ab is ever scaled.  A
+    // compile-time choice: a run-time branch here slows the unscaled kernels.
+    static_assert(!SCL || ((MODE == M_REONLY || MODE == M_KINT) && W == 2), "only a complex operand is scaled");
     T sre, sim;
     int cpc_log;          // log2 of chunks per stored column inside a tile
     int pos, col0;        // this thread's chunk 0: position in its column, column in the tile
@@ -199,7 +201,6 @@ struct Stage {
         // A is stored along m for 'N'/'R', B along n for 'T'/'C'
         mn_contig = FAST ? MNC : (IS_A ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2));
         conj = tr >= 2;
-        scl = CAN_SCALE && (IS_A ? g.a_scale : g.b_scale);
         sre = (T)g.scale_re;
         sim = (T)g.scale_im;
         ld = IS_A ? g.lda : g.ldb;
@@ -384,11 +385,9 @@ struct Stage {
     template <class Out>
     __device__ __forceinline__ void store_to(Out out) const {
         if (PARTIAL && !active) return;
-        if constexpr (CAN_SCALE) {
-            if (scl) {
-                store_scaled(out);
-                return;
-            }
+        if constexpr (SCL) {
+            store_scaled(out);
+            return;
         }
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
@@ -563,11 +562,13 @@ struct Frag {
 // faster for every configuration except FP64 on 4 waves (late store up to 5 %
 // faster there).
 
+// SCL: the complex operand of case 1a, 2ab (A) or 1b (B) is staged scaled by
+// the complex alpha (GemmArgs::scale_re/scale_im).
 template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<T>,
-          bool RAG = false>
+          bool RAG = false, bool SCL = false>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
-    typedef Stage<T, CS, true, FAST, AD, AMNC, C, RAG> SA;
-    typedef Stage<T, CS, false, FAST, BD, BMNC, C, RAG> SB;
+    typedef Stage<T, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B> SA;
+    typedef Stage<T, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B> SB;
     constexpr bool PIPE = C::PIPE;
     constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef typename AccT<T>::type acc_t;

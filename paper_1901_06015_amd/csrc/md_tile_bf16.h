@@ -81,11 +81,12 @@ __device__ __forceinline__ v4f mfma_bf16(bf16x8 x, bf16x8 y, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
 }
 
-template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<float>, bool RAG = false>
+template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<float>, bool RAG = false,
+          bool SCL = false>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     static_assert(C::BK == 32, "one 16x16x32 step per LDS tile");
-    typedef Stage<float, CS, true, FAST, AD, AMNC, C, RAG> SA;
-    typedef Stage<float, CS, false, FAST, BD, BMNC, C, RAG> SB;
+    typedef Stage<float, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B> SA;
+    typedef Stage<float, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B> SB;
     constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef LayBF<AMNC, C::BM> LA;
     typedef LayBF<BMNC, C::BN> LB;

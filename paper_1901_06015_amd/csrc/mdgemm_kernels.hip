@@ -24,40 +24,40 @@ typedef double KT;
 typedef float KT;
 #endif
 
-template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, bool RAG>
+template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, bool RAG, bool SCL>
 static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 #if MD_KT == 2
     if constexpr (tile_kind(PREC_BF16X3, CS, FAST) == 3)
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG>), dim3(nwg),
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG, SCL>), dim3(nwg),
                            dim3(Deep<float>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, TileCfg<float>, RAG>), dim3(nwg),
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, TileCfg<float>, RAG, SCL>), dim3(nwg),
                            dim3(NT), 0, s, a);
 #else
     constexpr int kind = tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST);
     if constexpr (kind == 1)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideN<KT>, RAG>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideN<KT>, RAG, SCL>), dim3(nwg),
                            dim3(WideN<KT>::NT), 0, s, a);
     else if constexpr (kind == 2)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideM<KT>, RAG>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideM<KT>, RAG, SCL>), dim3(nwg),
                            dim3(WideM<KT>::NT), 0, s, a);
     else if constexpr (kind == 3)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, Deep<KT>, RAG>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, Deep<KT>, RAG, SCL>), dim3(nwg),
                            dim3(Deep<KT>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, TileCfg<KT>, RAG>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, TileCfg<KT>, RAG, SCL>), dim3(nwg),
                            dim3(NT), 0, s, a);
 #endif
 }
 
-template <int CS, bool FAST, bool AMNC, bool BMNC, bool RAG>
+template <int CS, bool FAST, bool AMNC, bool BMNC, bool RAG, bool SCL>
 static void launch_v(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     if (a.a_dbl) {
-        if (a.b_dbl) launch_k<CS, FAST, true, true, AMNC, BMNC, RAG>(a, s, nwg);
-        else launch_k<CS, FAST, true, false, AMNC, BMNC, RAG>(a, s, nwg);
+        if (a.b_dbl) launch_k<CS, FAST, true, true, AMNC, BMNC, RAG, SCL>(a, s, nwg);
+        else launch_k<CS, FAST, true, false, AMNC, BMNC, RAG, SCL>(a, s, nwg);
     } else {
-        if (a.b_dbl) launch_k<CS, FAST, false, true, AMNC, BMNC, RAG>(a, s, nwg);
-        else launch_k<CS, FAST, false, false, AMNC, BMNC, RAG>(a, s, nwg);
+        if (a.b_dbl) launch_k<CS, FAST, false, true, AMNC, BMNC, RAG, SCL>(a, s, nwg);
+        else launch_k<CS, FAST, false, false, AMNC, BMNC, RAG, SCL>(a, s, nwg);
     }
 }
 
@@ -66,26 +66,39 @@ static void launch_v(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 // variant for operands stored along k whose columns end inside a chunk (never
 // the case when both are stored along m/n); the generic kernels read the
 // orientation from the arguments.
-template <int CS>
-static void launch_c(const GemmArgs &a, hipStream_t s, unsigned nwg) {
+template <int CS, bool SCL>
+static void launch_o(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     if (a.a_vec && a.b_vec) {
         const bool am = a.ta == 0 || a.ta == 3, bm = a.tb == 1 || a.tb == 2, rag = a.a_ragged || a.b_ragged;
         if (am) {
-            if (bm) launch_v<CS, true, true, true, false>(a, s, nwg);
-            else if (rag) launch_v<CS, true, true, false, true>(a, s, nwg);
-            else launch_v<CS, true, true, false, false>(a, s, nwg);
+            if (bm) launch_v<CS, true, true, true, false, SCL>(a, s, nwg);
+            else if (rag) launch_v<CS, true, true, false, true, SCL>(a, s, nwg);
+            else launch_v<CS, true, true, false, false, SCL>(a, s, nwg);
         } else {
             if (bm) {
-                if (rag) launch_v<CS, true, false, true, true>(a, s, nwg);
-                else launch_v<CS, true, false, true, false>(a, s, nwg);
+                if (rag) launch_v<CS, true, false, true, true, SCL>(a, s, nwg);
+                else launch_v<CS, true, false, true, false, SCL>(a, s, nwg);
             } else {
-                if (rag) launch_v<CS, true, false, false, true>(a, s, nwg);
-                else launch_v<CS, true, false, false, false>(a, s, nwg);
+                if (rag) launch_v<CS, true, false, false, true, SCL>(a, s, nwg);
+                else launch_v<CS, true, false, false, false, SCL>(a, s, nwg);
             }
         }
     } else {
-        launch_v<CS, false, true, true, false>(a, s, nwg);
+        launch_v<CS, false, true, true, false, SCL>(a, s, nwg);
     }
+}
+
+// Cases 1a, 1b and 2ab also have the variants that stage their complex operand
+// scaled by a complex alpha (the literal interpretation with C real).
+template <int CS>
+static void launch_c(const GemmArgs &a, hipStream_t s, unsigned nwg) {
+    if constexpr (CS == MD_CASE_1A || CS == MD_CASE_1B || CS == MD_CASE_2AB) {
+        if (a.a_scale || a.b_scale) {
+            launch_o<CS, true>(a, s, nwg);
+            return;
+        }
+    }
+    launch_o<CS, false>(a, s, nwg);
 }
 
 #define MD_PART_NAME2(t, c) launch_part_##t##_##c
