@@ -23,8 +23,7 @@ ERR_ARG = -1
 
 CASE_NAMES = ("0", "1b", "1a", "2ab", "1c", "2bc", "2ac", "3")
 
-_TAG = {"s": 0, "d": 1, "c": 2, "z": 3}
-_NP = {0: np.float32, 1: np.float64, 2: np.complex64, 3: np.complex128}
+_TAG = {"s": 0, "d": 1, "c": 2, "z": 3, "h": 4, "hc": 5}
 
 
 def build(src=_SRC, out=_LIB):
@@ -35,7 +34,7 @@ def build(src=_SRC, out=_LIB):
 
 
 def tag(dt):
-    """Storage tag 0..3 from 's','d','c','z' or an int."""
+    """Storage tag 0..5 from 's','d','c','z','h','hc' or an int."""
     return _TAG[dt] if isinstance(dt, str) else int(dt)
 
 

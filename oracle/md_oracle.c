@@ -38,9 +38,28 @@
 #define T_D 1
 #define T_C 2
 #define T_Z 3
+#define T_H 4   /* IEEE 754 binary16 */
+#define T_HC 5  /* complex binary16, interleaved re, im */
 
-static int tag_ok(int dt) { return dt >= T_S && dt <= T_Z; }
-static int tag_complex(int dt) { return dt == T_C || dt == T_Z; }
+static int tag_ok(int dt) { return dt >= T_S && dt <= T_HC; }
+static int tag_complex(int dt) { return dt == T_C || dt == T_Z || dt == T_HC; }
+
+/* The value of a binary16 bit pattern (1 sign, 5 exponent bits biased by 15,
+ * 10 fraction bits; exponent 0 = subnormal, 31 = infinity or NaN), exactly in
+ * double: the additional precision the paper's Section 4 discussion leaves
+ * room for. */
+static double half_value(uint16_t h)
+{
+    int sign = h >> 15, e = (h >> 10) & 31, f = h & 1023;
+    double v;
+    if (e == 0)
+        v = ldexp((double)f, -24);
+    else if (e == 31)
+        v = f ? NAN : INFINITY;
+    else
+        v = ldexp((double)(1024 + f), e - 25);
+    return sign ? -v : v;
+}
 
 /* Promote stored element (r, c) exactly to (re, im); (rs, cs) are the row and
  * column strides in elements of the operand's own type. */
@@ -57,6 +76,12 @@ static void fetch(const void *X, int dt, int64_t rs, int64_t cs, int64_t r, int6
     } else if (dt == T_C) {
         *re = (double)((const float *)X)[2 * idx];
         *im = (double)((const float *)X)[2 * idx + 1];
+    } else if (dt == T_H) {
+        *re = half_value(((const uint16_t *)X)[idx]);
+        *im = 0.0;
+    } else if (dt == T_HC) {
+        *re = half_value(((const uint16_t *)X)[2 * idx]);
+        *im = half_value(((const uint16_t *)X)[2 * idx + 1]);
     } else {
         *re = ((const double *)X)[2 * idx];
         *im = ((const double *)X)[2 * idx + 1];

@@ -12,7 +12,9 @@
  * call this.  It shares no code, header, table or helper with the GPU library.
  *
  * Storage tags: 0 = s (float), 1 = d (double), 2 = c (float complex,
- * interleaved re,im), 3 = z (double complex, interleaved).  Matrices are
+ * interleaved re,im), 3 = z (double complex, interleaved), 4 = h (IEEE
+ * binary16), 5 = hc (binary16 complex, interleaved): the half precision the
+ * paper's Section 4 summary names as the next storage precision.  Matrices are
  * column-major unless strides are given (md_oracle_gemm_gs); a leading
  * dimension or stride counts elements of the operand's own type.  Trans
  * letters: N, T, C (the BLAS) and R (conjugate without transposing).

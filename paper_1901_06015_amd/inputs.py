@@ -6,7 +6,8 @@ draw operands here, then hand the same host buffers to the GPU library and to
 the CPU oracle.
 
 A matrix is returned as a Fortran-ordered numpy array of shape (ld, cols) in
-its storage type (float32, float64, complex64 or complex128); the logical
+its storage type (float32, float64, complex64, complex128, float16, or the
+structured pair of float16 ``HALF_COMPLEX`` for complex half); the logical
 matrix is its first ``rows`` rows.  Rows beyond ``rows`` (the ld padding) are
 filled with ``pad`` so that tests can check they are never written.
 
@@ -20,13 +21,25 @@ the workloads add the variants below):
 """
 import numpy as np
 
-NP_DTYPE = {"s": np.float32, "d": np.float64, "c": np.complex64, "z": np.complex128}
-REAL_OF = {"s": np.float32, "d": np.float64, "c": np.float32, "z": np.float64}
+# complex binary16: interleaved (re, im) pairs, 4 bytes per element
+HALF_COMPLEX = np.dtype([("re", np.float16), ("im", np.float16)])
+NP_DTYPE = {"s": np.float32, "d": np.float64, "c": np.complex64, "z": np.complex128,
+            "h": np.float16, "hc": HALF_COMPLEX}
+REAL_OF = {"s": np.float32, "d": np.float64, "c": np.float32, "z": np.float64,
+           "h": np.float16, "hc": np.float16}
 TAGS = ("s", "d", "c", "z")
+HALF_TAGS = ("h", "hc")
 
 
 def is_complex(dt):
-    return dt in ("c", "z")
+    return dt in ("c", "z", "hc")
+
+
+def to_complex128(X):
+    """The stored values of any storage type as complex128 (exact)."""
+    if X.dtype == HALF_COMPLEX:
+        return X["re"].astype(np.float64) + 1j * X["im"].astype(np.float64)
+    return np.asarray(X, dtype=np.complex128)
 
 
 def _parts(rng, shape, dist):
@@ -46,11 +59,20 @@ def matrix(rows, cols, dt, seed, ld=None, dist="uniform", pad=0.0):
     ld = max(1, rows) if ld is None else ld
     assert ld >= max(1, rows)
     rng = np.random.Generator(np.random.PCG64(seed))
-    out = np.full((ld, cols), pad, dtype=NP_DTYPE[dt], order="F")
+    if dt == "hc":
+        out = np.zeros((ld, cols), dtype=HALF_COMPLEX, order="F")
+        out["re"] = pad
+        out["im"] = pad
+    else:
+        out = np.full((ld, cols), pad, dtype=NP_DTYPE[dt], order="F")
     if rows == 0 or cols == 0:
         return out
     re = _parts(rng, (cols, rows), dist).T
-    if is_complex(dt):
+    if dt == "hc":
+        im = _parts(rng, (cols, rows), dist).T
+        out["re"][:rows, :] = re.astype(np.float16)
+        out["im"][:rows, :] = im.astype(np.float16)
+    elif is_complex(dt):
         im = _parts(rng, (cols, rows), dist).T
         out[:rows, :] = (re.astype(REAL_OF[dt]) + 1j * im.astype(REAL_OF[dt])).astype(NP_DTYPE[dt])
     else:

@@ -63,7 +63,7 @@ def _dom_tags(is_cplx):
 def _op(X, rows, cols, trans):
     """op(X) as a complex128 array of the promoted stored values; "R" is the
     conjugate without transposition of Section 2's hypothetical API."""
-    M = np.asarray(X[:rows, :cols], dtype=np.complex128)
+    M = inputs.to_complex128(X[:rows, :cols])
     if trans == "N":
         return M
     if trans == "R":
@@ -476,9 +476,77 @@ def pin_literal_alpha(o):
     return fails
 
 
+def pin_half_decoding(o):
+    """IEEE binary16 storage: every finite bit pattern (zeros, subnormals,
+    normals) decodes to numpy's float16 value, as the real type h and as
+    either part of the complex type hc: the 63488 patterns fill a 256 x 256
+    matrix multiplied by the identity (alpha = 1, beta = 0; square, so an
+    index mistake stays inside the buffer).  NaN patterns give NaN (1 x 1
+    products).  Infinities are left out: the product is formed in complex
+    arithmetic, where inf * 0 in the imaginary part gives NaN."""
+    fails = []
+    n = 256
+    bits = np.arange(65536, dtype=np.uint16)
+    fin = bits[np.isfinite(bits.view(np.float16))]
+    grid = np.zeros(n * n, dtype=np.uint16)
+    grid[:fin.size] = fin
+    A = np.asfortranarray(grid.view(np.float16).reshape(n, n, order="F"))
+    eye = np.asfortranarray(np.eye(n))
+    C = np.zeros((n, n), dtype=np.complex128, order="F")
+    want = A.astype(np.float64)
+    st, got, _ = o.gemm("N", "N", n, n, n, 1.0, A, "h", n, eye, "d", n, 0.0, C, "z", n)
+    if st != 0 or not (np.array_equal(got.real, want) and np.all(got.imag == 0)):
+        fails.append("h decoding differs from numpy's float16")
+    Ac = np.zeros((n, n), dtype=inputs.HALF_COMPLEX, order="F")
+    Ac["re"] = A
+    Ac["im"] = np.asfortranarray(grid[::-1].copy().view(np.float16).reshape(n, n, order="F"))
+    st, got, _ = o.gemm("N", "N", n, n, n, 1.0, Ac, "hc", n, eye, "d", n, 0.0, C, "z", n)
+    if st != 0 or not (np.array_equal(got.real, want) and np.array_equal(got.imag, Ac["im"].astype(np.float64))):
+        fails.append("hc decoding differs from numpy's float16")
+    one = np.ones((1, 1), dtype=np.float64, order="F")
+    c1 = np.zeros((1, 1), dtype=np.complex128, order="F")
+    for nan_bits in (0x7C01, 0x7E00, 0xFE00, 0x7FFF):
+        x = np.array([[nan_bits]], dtype=np.uint16).view(np.float16)
+        st, got, _ = o.gemm("N", "N", 1, 1, 1, 1.0, np.asfortranarray(x), "h", 1, one, "d", 1, 0.0, c1, "z", 1)
+        if st != 0 or not np.isnan(got[0, 0].real):
+            fails.append("NaN pattern %#x did not decode to NaN" % nan_bits)
+    return fails
+
+
+def pin_half_products(o):
+    """Half storage in every role: with h and hc among the operands, every
+    storage combination of {h, hc, s, z} equals numpy's homogeneous complex
+    product of the promoted values (Re kept for a real C) -- exactly for
+    integer inputs -- and takes the case and flop count of its domains."""
+    fails = []
+    alpha, beta = 1.5, -0.5
+    m, n, k = 4, 5, 6
+    for i, (tc, ta_, tb_) in enumerate(itertools.product(("h", "hc", "s", "z"), repeat=3)):
+        if "h" not in (tc, ta_, tb_) and "hc" not in (tc, ta_, tb_):
+            continue
+        doms = tuple(inputs.is_complex(t) for t in (tc, ta_, tb_))
+        if o.case(tc, ta_, tb_) != o.case(*("z" if d else "d" for d in doms)):
+            fails.append("case of %s/%s/%s" % (tc, ta_, tb_))
+        ta, tb = ("N", "T", "C", "R")[i % 4], ("R", "C", "N", "T")[i % 4]
+        for dist in ("int", "uniform"):
+            A, B, C, _, _ = _operands(ta_, tb_, tc, m, n, k, ta, tb, seed=500 + i, dist=dist)
+            st, got, _ = o.gemm(ta, tb, m, n, k, alpha, A, ta_, A.shape[0], B, tb_, B.shape[0], beta, C, tc,
+                                C.shape[0])
+            ac = (m, k) if ta in "NR" else (k, m)
+            bc = (k, n) if tb in "NR" else (n, k)
+            want = alpha * (_op(A, ac[0], ac[1], ta) @ _op(B, bc[0], bc[1], tb)) + \
+                beta * inputs.to_complex128(C[:m, :n])
+            if not inputs.is_complex(tc):
+                want = want.real.astype(np.complex128)
+            ok = np.array_equal(got, want) if dist == "int" else np.allclose(got, want, rtol=0, atol=1e-12)
+            if st != 0 or not ok:
+                fails.append("half %s/%s/%s %s%s (%s) status %d" % (tc, ta_, tb_, ta, tb, dist, st))
+    return fails
+
+
 ALL_PINS = (pin_case_table, pin_flops, pin_same_type, pin_domain_identities,
             pin_exact_integers, pin_exact_rational, pin_1m_equations, pin_scalars,
-            pin_transpose, pin_strides, pin_literal_alpha)
+            pin_transpose, pin_strides, pin_literal_alpha, pin_half_decoding, pin_half_products)
 
 
 def run_all(o):

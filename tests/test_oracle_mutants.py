@@ -39,6 +39,11 @@ MUTANTS = {
                               "if (alpha_refused(dtc, dta, dtb, alpha_im))"),
     "alpha_projected_in_mixed_cases": ("if (md_oracle_case(dtc, dta, dtb) == 0)",
                                        "if (md_oracle_case(dtc, dta, dtb) != 7)"),
+    "half_exponent_bias": ("v = ldexp((double)(1024 + f), e - 25);", "v = ldexp((double)(1024 + f), e - 24);"),
+    "half_implicit_bit_dropped": ("v = ldexp((double)(1024 + f), e - 25);", "v = ldexp((double)f, e - 15);"),
+    "half_subnormal_scale": ("v = ldexp((double)f, -24);", "v = ldexp((double)f, -25);"),
+    "half_complex_parts_swapped": ("*im = half_value(((const uint16_t *)X)[2 * idx + 1]);",
+                                   "*im = half_value(((const uint16_t *)X)[2 * idx]);"),
     "flops_case2": ("double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 4.0 : 8.0);",
                     "double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 8.0 : 8.0);"),
 }
