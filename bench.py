@@ -273,7 +273,8 @@ def cpu_baseline(budget_s):
 
 
 def precision_workload(args):
-    """FP32 MFMA vs BF16x3 at m=n=k=size (8192 by default) for ssss, csss,
+    """FP32 MFMA vs BF16x3 (and, beside them, the half computation precision
+    on the fp16 matrix cores) at m=n=k=size (8192 by default) for ssss, csss,
     ccss, cccs (the cab(x) reading of the combinations) and scss, sccs (the
     other reading), each with U[-1,1] and log-uniform 10^U(-3,3) entries,
     alpha = 1, beta = 0.  Errors: against the CPU oracle on 512 sampled
@@ -290,7 +291,7 @@ def precision_workload(args):
     rows = np.concatenate([[0, n - 1, 0, n - 1, 127, 128], rng.integers(0, n, 506)]).astype(np.int64)
     cols = np.concatenate([[0, 0, n - 1, n - 1, 128, 127], rng.integers(0, n, 506)]).astype(np.int64)
     out = {}
-    total = {"s": [0.0, 0.0], "bf16x3": [0.0, 0.0]}
+    total = {"s": [0.0, 0.0], "bf16x3": [0.0, 0.0], "h": [0.0, 0.0]}
     for cab in ("sss", "css", "ccs", "ccc", "scs", "scc"):
         for dist in ("uniform", "loguniform"):
             tc, ta, tb = cab
@@ -313,7 +314,7 @@ def precision_workload(args):
             lib_ref = Cref[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
             ref_check = float(np.max(np.abs(lib_ref - ref_s) / np.maximum(g_s, 1e-300)))
             res = {"fp64_reference_vs_oracle_max_rel": ref_check}
-            for comp in ("s", "bf16x3"):
+            for comp in ("s", "bf16x3", "h"):
                 dC = torch.from_numpy(C0).cuda()
                 ts = []
                 for r in range(1 + args.steps):
@@ -332,7 +333,10 @@ def precision_workload(args):
                 gf = pl["flops"] / p50 / 1e9
                 got = dC[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.complex128)
                 err = np.abs(got - ref_s)
-                bound = 4 * n * 2.0 ** -24 * g_s + 4 * (2.0 ** -24 if tc in "sc" else 2.0 ** -53) * np.abs(ref_s)
+                # single-precision bound; for half, operands rounded to binary16
+                # and FP32 accumulation
+                ux_term = (4 * 2.0 ** -11 + 4 * n * 2.0 ** -24) if comp == "h" else 4 * n * 2.0 ** -24
+                bound = ux_term * g_s + 4 * (2.0 ** -24 if tc in "sc" else 2.0 ** -53) * np.abs(ref_s)
                 full = dC.to(torch.complex128)
                 nf = float(torch.linalg.norm(full - Cref) / torch.linalg.norm(Cref))
                 del full, dC
@@ -355,8 +359,11 @@ def precision_workload(args):
                                    "U[-1,1] and 10^U(-3,3), alpha=1, beta=0" % n},
             "fp32_gflops": round(agg["s"], 1),
             "speedup_bf16x3_over_fp32": round(agg["bf16x3"] / agg["s"], 3),
+            "half_gflops": round(agg["h"], 1),
+            "speedup_half_over_fp32": round(agg["h"] / agg["s"], 3),
             "roofline": {"bf16x3_vs_fp32_peak": round(agg["bf16x3"] / 157.3e3, 4),
-                         "bf16_mfma_utilisation": round(3 * agg["bf16x3"] / 2.5e6, 4)},
+                         "bf16_mfma_utilisation": round(3 * agg["bf16x3"] / 2.5e6, 4),
+                         "f16_mfma_utilisation": round(agg["h"] / 2.5e6, 4)},
             "per_combo": out}
     print(json.dumps(line), flush=True)
 

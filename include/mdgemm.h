@@ -38,7 +38,14 @@ extern "C" {
 #endif
 
 /* Storage type of one operand (domain x precision, Section 1's s/d/c/z). */
-typedef enum { MD_S = 0, MD_D = 1, MD_C = 2, MD_Z = 3 } md_dt;
+typedef enum {
+    MD_S = 0, MD_D = 1, MD_C = 2, MD_Z = 3,
+    /* Half precision, the next storage precision Section 4's summary names
+     * (an addition of this library): IEEE 754 binary16 (MD_H) and complex
+     * binary16 with interleaved re, im (MD_HC).  Operands and C of these
+     * types are served by the component-wise loads and their epilogue. */
+    MD_H = 4, MD_HC = 5
+} md_dt;
 
 /* Computation precision (Section 4.1.1).  MD_COMP_DEFAULT selects the storage
  * precision of C.  MD_COMP_S_BF16X3 has single-precision semantics but forms
@@ -50,6 +57,12 @@ typedef enum {
     MD_COMP_S = 0,
     MD_COMP_D = 1,
     MD_COMP_S_BF16X3 = 2,
+    /* Half computation precision (an addition of this library): each
+     * element of A and B is rounded to binary16 (nearest even) as it is
+     * staged and the products run on the fp16 matrix cores with FP32
+     * accumulation; alpha, beta and the update follow the single rules.  The
+     * default for a half-precision C. */
+    MD_COMP_H = 3,
     /* Flag, OR'ed into MD_COMP_S, MD_COMP_D or MD_COMP_S_BF16X3 (not into
      * MD_COMP_DEFAULT): a complex alpha is applied as given in the six mixed
      * cases too, under the literal interpretation Section 6.2 describes (all

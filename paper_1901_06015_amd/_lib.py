@@ -13,13 +13,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # compiled with different tuning knobs).
 LIB_PATH = os.environ.get("MDGEMM_LIBRARY", os.path.join(HERE, "libmdgemm.so"))
 
-MD_S, MD_D, MD_C, MD_Z = 0, 1, 2, 3
-MD_COMP_DEFAULT, MD_COMP_S, MD_COMP_D, MD_COMP_S_BF16X3 = -1, 0, 1, 2
+MD_S, MD_D, MD_C, MD_Z, MD_H, MD_HC = 0, 1, 2, 3, 4, 5
+MD_COMP_DEFAULT, MD_COMP_S, MD_COMP_D, MD_COMP_S_BF16X3, MD_COMP_H = -1, 0, 1, 2, 3
 MD_OK, MD_ERR_ALPHA_IMAG, MD_ERR_HIP, MD_ERR_BUDGET, MD_ERR_STATE, MD_ERR_UNSUPPORTED = 0, 1, 2, 3, 4, 5
 CASE_NAMES = ("0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3")
-DT_TAG = {"s": MD_S, "d": MD_D, "c": MD_C, "z": MD_Z}
+DT_TAG = {"s": MD_S, "d": MD_D, "c": MD_C, "z": MD_Z, "h": MD_H, "hc": MD_HC}
 COMP_TAG = {None: MD_COMP_DEFAULT, "default": MD_COMP_DEFAULT, "s": MD_COMP_S, "d": MD_COMP_D,
-            "bf16x3": MD_COMP_S_BF16X3}
+            "bf16x3": MD_COMP_S_BF16X3, "h": MD_COMP_H}
 
 
 class MdScalar(ctypes.Structure):
@@ -102,8 +102,8 @@ def comp_tag(comp):
         return COMP_TAG[comp] if comp is None else int(comp)
     if comp.endswith("+literal"):
         base = comp[:-len("+literal")]
-        if base not in ("s", "d", "bf16x3"):
-            raise ValueError("the literal-alpha flag needs an explicit precision (s, d or bf16x3)")
+        if base not in ("s", "d", "bf16x3", "h"):
+            raise ValueError("the literal-alpha flag needs an explicit precision (s, d, bf16x3 or h)")
         return COMP_TAG[base] | MD_COMP_LITERAL_ALPHA
     return COMP_TAG[comp]
 

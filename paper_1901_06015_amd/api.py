@@ -6,14 +6,15 @@ strides to ``mdgemm_strided`` (the strided interface sketched in Section 2 of
 the paper).  ``plan`` and grouped calls take column-major tensors, the BLAS
 layout of Section 1 (leading dimension ``stride(1)``); ``colmajor`` makes one.
 The storage type follows the tensor dtype: float32 -> s, float64 -> d,
-complex64 -> c, complex128 -> z.  op is one of N, T, C (conjugate transpose)
+complex64 -> c, complex128 -> z, float16 -> h, complex32 -> hc (binary16).  op is one of N, T, C (conjugate transpose)
 and R (conjugate without transposing).
 """
 import torch
 
 from . import _lib
 
-_DT = {torch.float32: "s", torch.float64: "d", torch.complex64: "c", torch.complex128: "z"}
+_DT = {torch.float32: "s", torch.float64: "d", torch.complex64: "c", torch.complex128: "z",
+       torch.float16: "h", torch.complex32: "hc"}
 _TORCH = {v: k for k, v in _DT.items()}
 
 
@@ -27,7 +28,8 @@ def dt_of(t):
     try:
         return _DT[t.dtype]
     except KeyError:
-        raise TypeError("unsupported dtype %s (use float32/float64/complex64/complex128)" % t.dtype)
+        raise TypeError("unsupported dtype %s (use float32/float64/complex64/complex128/float16/complex32)"
+                        % t.dtype)
 
 
 def torch_dtype(dt):

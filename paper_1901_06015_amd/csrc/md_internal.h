@@ -38,7 +38,8 @@ inline Lowering lower_case(int cs) {
 }
 
 inline int classify(int dtc, int dta, int dtb) {
-    bool c = dtc >= MD_C, a = dta >= MD_C, b = dtb >= MD_C;
+    auto cplx = [](int dt) { return dt == MD_C || dt == MD_Z || dt == MD_HC; };
+    const bool c = cplx(dtc), a = cplx(dta), b = cplx(dtb);
     if (!c && !a && !b) return MD_CASE_0;
     if (!c && a && !b) return MD_CASE_1A;
     if (!c && !a && b) return MD_CASE_1B;
@@ -63,6 +64,7 @@ struct GemmArgs {
                             // component-wise loads and their epilogue take
     int64_t m, n, k;
     int a_dbl, b_dbl, c_dbl;  // storage precision is double
+    int a_half, b_half, c_half;  // storage precision is binary16 (component-wise path only)
     int c_cplx;               // C is complex
     int ta, tb;               // 0 = 'N', 1 = 'T', 2 = 'C', 3 = 'R' (conjugate, not transposed)
     int a_vec, b_vec;         // the operand can be staged in 16-byte chunks
@@ -75,7 +77,7 @@ struct GemmArgs {
     int tiles_m, tiles_n;     // workgroup tiles of the real product
 };
 
-enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
+enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2, PREC_H = 3 };
 
 // Tile configuration of the plain product kernel for (computation precision,
 // case, fast load path): 0 = 128 x 128 tiles of 4 waves, 1 = 128 x 256 and
@@ -94,7 +96,7 @@ enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2 };
 #endif
 constexpr int tile_kind(int prec, int cs, bool fast) {
     return !fast ? 0
-         : prec == PREC_BF16X3 ? (MD_BF16X3_DEEP ? 3 : 0)
+         : (prec == PREC_BF16X3 || prec == PREC_H) ? (MD_BF16X3_DEEP ? 3 : 0)
          : (MD_WIDE & (prec == PREC_D ? 1 : 2)) ? 1
          : (MD_WIDE & (prec == PREC_D ? 4 : 8)) ? 2
          : (MD_WIDE & (prec == PREC_D ? 16 : 32)) ? 3 : 0 * cs;

@@ -21,7 +21,7 @@
 
 namespace {
 
-int elem_bytes(int dt) { return dt == MD_S ? 4 : (dt == MD_Z ? 16 : 8); }
+int elem_bytes(int dt) { return dt == MD_H ? 2 : (dt == MD_S || dt == MD_HC) ? 4 : (dt == MD_Z ? 16 : 8); }
 
 // Size class of a device block: 4 KiB minimum, then four classes per power of
 // two, so a block wastes less than a quarter of its size.
@@ -363,7 +363,7 @@ int md_server_destroy(md_server *s) {
 }
 
 int md_server_put(md_server *s, const void *host, md_dt dt, int64_t rows, int64_t cols, int64_t *handle) {
-    if (!s || !handle || !host || rows < 0 || cols < 0 || dt < MD_S || dt > MD_Z) return MD_ERR_STATE;
+    if (!s || !handle || !host || rows < 0 || cols < 0 || dt < MD_S || dt > MD_HC) return MD_ERR_STATE;
     Operand o;
     o.dt = dt;
     o.rows = rows;

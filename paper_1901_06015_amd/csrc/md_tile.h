@@ -33,6 +33,7 @@
 
 #include <type_traits>
 
+#include "md_half.h"
 #include "md_internal.h"
 
 namespace md {
@@ -152,8 +153,10 @@ __device__ __forceinline__ int split_pos(int mm, int q) { return (((mm >> 4) << 
 // RAG (fast path only): the operand's columns may end inside a chunk; an
 // operand stored contiguous along k then masks what a chunk reads past them.
 // SCL: the operand is staged as (scale_re + i scale_im) times itself.
+// RTO: double components become float by round-to-odd (float_rto), for the
+// half kernels, which round the staged float once more to binary16.
 template <class T, int CS, bool IS_A, bool FAST, bool SDBL, bool MNC, class C = TileCfg<T>, bool RAG = false,
-          bool SCL = false>
+          bool SCL = false, bool RTO = false>
 struct Stage {
     static constexpr int MODE = mode_of<CS, IS_A>();
     static constexpr int W = (MODE == M_PLAIN) ? 1 : 2;  // stored components per element
@@ -184,6 +187,7 @@ struct Stage {
 
     const char *base;
     int64_t ld, rs, MN, K, mn0;  // rs: element stride along a stored column (generic path)
+    bool half;                   // binary16 storage (generic path, single-width components)
     int64_t total_bytes;  // extent of the stored matrix
     bool mn_contig, conj;
     // Scaling by a complex alpha while staging (literal interpretation, real C):
@@ -205,6 +209,7 @@ struct Stage {
         sim = (T)g.scale_im;
         ld = IS_A ? g.lda : g.ldb;
         rs = IS_A ? g.rsa : g.rsb;
+        half = !SDBL && (IS_A ? g.a_half : g.b_half);
         MN = IS_A ? g.m : g.n;
         K = g.k;
         mn0 = mn0_;
@@ -284,6 +289,15 @@ struct Stage {
                 if (colok && comp0 + 0 < contig_len) e0 = p[at(comp0 + 0)];
                 if (colok && comp0 + 1 < contig_len) e1 = p[at(comp0 + 1)];
                 raw[c] = make_uint4(e0.x, e0.y, e1.x, e1.y);
+            } else if (half) {
+                // binary16 components widened exactly to float in the chunk registers
+                const _Float16 *p = (const _Float16 *)base + cbase;
+                uint32_t e0 = 0u, e1 = 0u, e2 = 0u, e3 = 0u;
+                if (colok && comp0 + 0 < contig_len) e0 = __float_as_uint((float)p[at(comp0 + 0)]);
+                if (colok && comp0 + 1 < contig_len) e1 = __float_as_uint((float)p[at(comp0 + 1)]);
+                if (colok && comp0 + 2 < contig_len) e2 = __float_as_uint((float)p[at(comp0 + 2)]);
+                if (colok && comp0 + 3 < contig_len) e3 = __float_as_uint((float)p[at(comp0 + 3)]);
+                raw[c] = make_uint4(e0, e1, e2, e3);
             } else {
                 const uint32_t *p = (const uint32_t *)base + cbase;
                 uint32_t e0 = 0u, e1 = 0u, e2 = 0u, e3 = 0u;
@@ -307,7 +321,9 @@ struct Stage {
         if constexpr (SDBL) {
             const uint32_t w0 = q ? h.z : h.x;
             const uint32_t w1 = q ? h.w : h.y;
-            return (T)__builtin_bit_cast(double, ((uint64_t)w1 << 32) | w0);
+            const double d = __builtin_bit_cast(double, ((uint64_t)w1 << 32) | w0);
+            if constexpr (RTO) return (T)float_rto(d);
+            else return (T)d;
         } else {
             const uint32_t w = q == 0 ? h.x : (q == 1 ? h.y : (q == 2 ? h.z : h.w));
             return (T)__builtin_bit_cast(float, w);
@@ -449,6 +465,15 @@ __device__ __forceinline__ void update_real(const GemmArgs &g, int64_t i, int64_
     if (i >= g.m || j >= g.n) return;
     const int64_t off = c_offset<GS>(g, i, j);
     const T ax = (T)g.alpha_re;
+    if constexpr (GS) {
+        if (g.c_half) {
+            // beta is already binary16; the update in double, one rounding to binary16
+            _Float16 *c = (_Float16 *)g.C;
+            const double t = (double)(ax * acc);
+            c[off] = half_rn(g.beta_zero ? t : fma(g.beta_re, (double)((const _Float16 *)g.Cin)[off], t));
+            return;
+        }
+    }
     if (g.c_dbl) {
         double *c = (double *)g.C;
         const double *cin = (const double *)g.Cin;
@@ -489,6 +514,25 @@ __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_
     if (i >= g.m || j >= g.n) return;
     const int64_t off = 2 * c_offset<GS>(g, i, j);
     const T ar = (T)g.alpha_re, ai = (T)g.alpha_im;
+    if constexpr (GS) {
+        if (g.c_half) {
+            // alpha*AB in the computation precision, the beta update in double,
+            // one rounding to binary16 per part
+            _Float16 *c = (_Float16 *)g.C + off;
+            const _Float16 *cin = (const _Float16 *)g.Cin + off;
+            const double tr = (double)fma(ar, re, -(ai * im));
+            const double ti = (double)fma(ar, im, ai * re);
+            double rr = tr, ri = ti;
+            if (!g.beta_zero) {
+                const double br = g.beta_re, bi = g.beta_im, cr = (double)cin[0], ci = (double)cin[1];
+                rr = fma(br, cr, fma(-bi, ci, tr));
+                ri = fma(br, ci, fma(bi, cr, ti));
+            }
+            c[0] = half_rn(rr);
+            c[1] = half_rn(ri);
+            return;
+        }
+    }
     if (g.c_dbl) {
         double *c = (double *)g.C + off;
         // beta is already double (C's precision); product in double.

@@ -12,6 +12,10 @@
 // domain cases, the staging loads and the epilogue are those of md_tile.h with
 // T = float.  This precision form is an addition of this library, not of the
 // paper.
+//
+// With H16 the same kernel is the half computation precision (MD_COMP_H):
+// staging rounds each FP32 value to binary16 into one LDS plane and every
+// 16x16x32 step is one v_mfma_f32_16x16x32_f16 with FP32 accumulation.
 #pragma once
 #include "md_tile.h"
 
@@ -60,6 +64,16 @@ __device__ __forceinline__ bf16x4 lds_read_tr16(const __bf16 *p) {
 // k = 8g + j (then 8g + j + 4) at columns 4a .. 4a+3 of the block, so lane
 // 16g + r receives the 4 consecutive k of column r; from a [mn][k] plane the
 // 8 k are one 16-byte read.
+// Staging output that rounds each FP32 value to binary16 (nearest even).
+template <bool MNC, int BMN>
+struct HalfOut {
+    typedef LayBF<MNC, BMN> L;
+    __bf16 *plane;  // 16-bit LDS storage, written as binary16
+    __device__ __forceinline__ void put(int kk, int mm, float v) const {
+        ((_Float16 *)plane)[L::at(kk, mm)] = (_Float16)v;
+    }
+};
+
 template <bool MNC, int BMN>
 __device__ __forceinline__ bf16x8 read_bf16_frag(const __bf16 *plane, int lane, int w0, int i) {
     typedef LayBF<MNC, BMN> L;
@@ -81,12 +95,20 @@ __device__ __forceinline__ v4f mfma_bf16(bf16x8 x, bf16x8 y, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
 }
 
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// The same fragments (16-bit lanes) taken as binary16.
+__device__ __forceinline__ v4f mfma_f16(bf16x8 x, bf16x8 y, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c, 0,
+                                                  0, 0);
+}
+
 template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<float>, bool RAG = false,
-          bool SCL = false>
+          bool SCL = false, bool H16 = false>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     static_assert(C::BK == 32, "one 16x16x32 step per LDS tile");
-    typedef Stage<float, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B> SA;
-    typedef Stage<float, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B> SB;
+    typedef Stage<float, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B, H16 && AD> SA;
+    typedef Stage<float, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B, H16 && BD> SB;
     constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef LayBF<AMNC, C::BM> LA;
     typedef LayBF<BMNC, C::BN> LB;
@@ -94,9 +116,10 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     constexpr bool MDBL = SA::MN2, NDBL = SB::MN2;
     constexpr bool CCPLX = (CS == MD_CASE_1C || CS == MD_CASE_2AC || CS == MD_CASE_2BC || CS == MD_CASE_3);
 
-    // [buffer][plane hi/lo][...]
-    __shared__ __attribute__((aligned(16))) __bf16 sA[2][2][LA::SIZE];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][LB::SIZE];
+    // [buffer][plane hi/lo (one binary16 plane with H16)][...]
+    constexpr int NPL = H16 ? 1 : 2;
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][NPL][LA::SIZE];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][NPL][LB::SIZE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave % C::WGM) * (C::BM / C::WGM), wn0 = (wave / C::WGM) * (C::BN / C::WGN);
@@ -114,8 +137,13 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     SA la(g, tid, mn0a);
     SB lb(g, tid, mn0b);
     auto stage_out = [&](int buf) {
-        la.store_to(SplitOut<AMNC, C::BM>{sA[buf][0], sA[buf][1]});
-        lb.store_to(SplitOut<BMNC, C::BN>{sB[buf][0], sB[buf][1]});
+        if constexpr (H16) {
+            la.store_to(HalfOut<AMNC, C::BM>{sA[buf][0]});
+            lb.store_to(HalfOut<BMNC, C::BN>{sB[buf][0]});
+        } else {
+            la.store_to(SplitOut<AMNC, C::BM>{sA[buf][0], sA[buf][NPL - 1]});
+            lb.store_to(SplitOut<BMNC, C::BN>{sB[buf][0], sB[buf][NPL - 1]});
+        }
     };
     // One LDS tile = one 32-deep step: 3 bf16 MFMAs per 16x16 block.
     auto tile = [&](int cur, bool store_next) {
@@ -123,21 +151,25 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < WMB; ++i) {
             ah[i] = read_bf16_frag<AMNC, C::BM>(sA[cur][0], lane, wm0, i);
-            al[i] = read_bf16_frag<AMNC, C::BM>(sA[cur][1], lane, wm0, i);
+            if constexpr (!H16) al[i] = read_bf16_frag<AMNC, C::BM>(sA[cur][NPL - 1], lane, wm0, i);
         }
 #pragma unroll
         for (int i = 0; i < WNB; ++i) {
             bh[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][0], lane, wn0, i);
-            bl[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][1], lane, wn0, i);
+            if constexpr (!H16) bl[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][NPL - 1], lane, wn0, i);
         }
         if (store_next) stage_out(cur ^ 1);
 #pragma unroll
         for (int a = 0; a < WMB; ++a)
 #pragma unroll
             for (int b = 0; b < WNB; ++b) {
-                acc[a][b] = mfma_bf16(bl[b], ah[a], acc[a][b]);
-                acc[a][b] = mfma_bf16(bh[b], al[a], acc[a][b]);
-                acc[a][b] = mfma_bf16(bh[b], ah[a], acc[a][b]);
+                if constexpr (H16) {
+                    acc[a][b] = mfma_f16(bh[b], ah[a], acc[a][b]);
+                } else {
+                    acc[a][b] = mfma_bf16(bl[b], ah[a], acc[a][b]);
+                    acc[a][b] = mfma_bf16(bh[b], al[a], acc[a][b]);
+                    acc[a][b] = mfma_bf16(bh[b], ah[a], acc[a][b]);
+                }
             }
     };
 

@@ -20,7 +20,7 @@ int norm_trans(char t) {
     return -1;
 }
 
-bool dt_ok(int dt) { return dt >= MD_S && dt <= MD_Z; }
+bool dt_ok(int dt) { return dt >= MD_S && dt <= MD_HC; }
 
 // A computation precision, optionally with MD_COMP_LITERAL_ALPHA OR'ed into an
 // explicit one.
@@ -28,7 +28,7 @@ bool comp_ok(int comp) {
     if (comp == MD_COMP_DEFAULT) return true;
     if (comp < 0) return false;
     const int base = comp & ~MD_COMP_LITERAL_ALPHA;
-    return base == MD_COMP_S || base == MD_COMP_D || base == MD_COMP_S_BF16X3;
+    return base == MD_COMP_S || base == MD_COMP_D || base == MD_COMP_S_BF16X3 || base == MD_COMP_H;
 }
 
 // The op of an operand after swapping its row and column strides (its
@@ -71,9 +71,9 @@ int storage_view(int64_t rows, int64_t cols, int64_t rs, int64_t cs, View *v) {
     else return rs <= cs ? 2 : 1;
     return 0;
 }
-bool dt_cplx(int dt) { return dt == MD_C || dt == MD_Z; }
+bool dt_cplx(int dt) { return dt == MD_C || dt == MD_Z || dt == MD_HC; }
 bool dt_dbl(int dt) { return dt == MD_D || dt == MD_Z; }
-int dt_bytes(int dt) { return dt == MD_S ? 4 : (dt == MD_Z ? 16 : 8); }
+bool dt_half(int dt) { return dt == MD_H || dt == MD_HC; }
 int64_t max1(int64_t v) { return v > 1 ? v : 1; }
 
 }  // namespace
@@ -111,8 +111,10 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     if (literal) comp &= ~MD_COMP_LITERAL_ALPHA;
 
     // Section 4.1.1: the computation precision defaults to C's storage precision.
-    if (comp == MD_COMP_DEFAULT) comp = dt_dbl(dtc) ? MD_COMP_D : MD_COMP_S;
-    d.prec = comp == MD_COMP_D ? PREC_D : (comp == MD_COMP_S ? PREC_S : PREC_BF16X3);
+    if (comp == MD_COMP_DEFAULT) comp = dt_dbl(dtc) ? MD_COMP_D : (dt_half(dtc) ? MD_COMP_H : MD_COMP_S);
+    d.prec = comp == MD_COMP_D ? PREC_D
+           : comp == MD_COMP_S ? PREC_S
+           : comp == MD_COMP_H ? PREC_H : PREC_BF16X3;
     d.cs = classify(dtc, dta, dtb);
 
     // Section 6.2: Im(alpha) is projected away in case 0, used in case 3 and
@@ -136,7 +138,8 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     // Section 6.2: Im(beta) cannot change a real C.
     double bre = beta.re, bim = dt_cplx(dtc) ? beta.im : 0.0;
     // Section 6.1 option (1): beta takes C's storage precision.
-    if (!dt_dbl(dtc)) { bre = (double)(float)bre; bim = (double)(float)bim; }
+    if (dt_half(dtc)) { bre = (double)(_Float16)bre; bim = (double)(_Float16)bim; }
+    else if (!dt_dbl(dtc)) { bre = (double)(float)bre; bim = (double)(float)bim; }
 
     GemmArgs &g = d.g;
     g.A = A; g.B = B; g.C = C; g.Cin = C;
@@ -144,6 +147,7 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     g.rsa = rsa; g.rsb = rsb; g.rsc = rsc;
     g.m = m; g.n = n; g.k = k;
     g.a_dbl = dt_dbl(dta); g.b_dbl = dt_dbl(dtb); g.c_dbl = dt_dbl(dtc);
+    g.a_half = dt_half(dta); g.b_half = dt_half(dtb); g.c_half = dt_half(dtc);
     g.c_cplx = dt_cplx(dtc);
     g.ta = ta; g.tb = tb;
     // The fast kernels stage 16-byte chunks with buffer loads, which need only
@@ -156,11 +160,11 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     const int wa = dt_cplx(dta) ? 2 : 1, wb = dt_cplx(dtb) ? 2 : 1;
     const int cwa = dt_dbl(dta) ? 2 : 4, cwb = dt_dbl(dtb) ? 2 : 4;  // components per chunk
     const int64_t max_ld = ((int64_t)1 << 31) / (128 * 16) - 64;
-    // General storage (an element stride along the column, for any operand) takes
-    // the component-wise path.
-    const bool plain_c = rsc == 1;
-    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld && rsa == 1 && plain_c;
-    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld && rsb == 1 && plain_c;
+    // General storage (an element stride along the column, for any operand) and
+    // half-precision storage (any operand or C) take the component-wise path.
+    const bool plain_c = rsc == 1 && !dt_half(dtc);
+    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld && rsa == 1 && plain_c && !dt_half(dta);
+    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld && rsb == 1 && plain_c && !dt_half(dtb);
     g.a_ragged = (ta == 1 || ta == 2) && (k * wa) % cwa != 0;
     g.b_ragged = (tb == 0 || tb == 3) && (k * wb) % cwb != 0;
     g.alpha_re = are; g.alpha_im = aim;
@@ -268,7 +272,9 @@ int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     out->status = d.status;
     if (d.status < 0) return d.status;
     out->domain_case = d.cs;
-    out->comp = d.prec == PREC_D ? MD_COMP_D : (d.prec == PREC_S ? MD_COMP_S : MD_COMP_S_BF16X3);
+    out->comp = d.prec == PREC_D ? MD_COMP_D
+              : d.prec == PREC_S ? MD_COMP_S
+              : d.prec == PREC_H ? MD_COMP_H : MD_COMP_S_BF16X3;
     if (d.status != MD_OK) return d.status;
     out->quick = d.quick;
     const Lowering L = lower_case(d.cs);

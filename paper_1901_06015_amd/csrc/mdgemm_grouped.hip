@@ -81,9 +81,11 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         // the grouped kernel addresses an operand tile with 32-bit offsets:
         // 128 columns of 32 components of 16 bytes must span less than 2 GiB;
         // it also does not scale an operand while staging it (a complex alpha
-        // under the literal interpretation with C real)
-        if (d.quick == 0 && (x.lda >= ((int64_t)1 << 20) || x.ldb >= ((int64_t)1 << 20) || d.g.a_scale ||
-                             d.g.b_scale)) {
+        // under the literal interpretation with C real), read or write
+        // binary16 storage, or compute in half precision
+        if ((d.quick == 0 && (x.lda >= ((int64_t)1 << 20) || x.ldb >= ((int64_t)1 << 20) || d.g.a_scale ||
+                              d.g.b_scale || d.g.a_half || d.g.b_half || d.prec == PREC_H)) ||
+            d.g.c_half) {
             alone.push_back(i);
             continue;
         }

@@ -1,10 +1,10 @@
 // mdgemm_kernels.hip -- instantiations of the product kernel (md_tile.h).
 //
 // Compiled once per (computation precision, domain case) with
-// -DMD_KT=<0 single | 1 double | 2 BF16x3> and -DMD_KCASE=<md_case> so that the 128
-// variants (3 computation precisions x 8 cases x 4 storage precisions of A and
-// B x 5 load paths: the fast path for each of the 4 operand orientations and
-// the generic path) build in parallel.
+// -DMD_KT=<0 single | 1 double | 2 BF16x3 | 3 half> and -DMD_KCASE=<md_case> so
+// that the variants (4 computation precisions x 8 cases x 4 storage precisions
+// of A and B x 5 load paths: the fast path for each of the 4 operand
+// orientations and the generic path) build in parallel.
 #include "md_tile.h"
 #include "md_tile_bf16.h"
 
@@ -17,7 +17,7 @@
 
 namespace md {
 
-// MD_KT: 0 = single (FP32 MFMA), 1 = double (FP64 MFMA), 2 = BF16x3.
+// MD_KT: 0 = single (FP32 MFMA), 1 = double (FP64 MFMA), 2 = BF16x3, 3 = half (FP16 MFMA).
 #if MD_KT == 1
 typedef double KT;
 #else
@@ -26,13 +26,14 @@ typedef float KT;
 
 template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, bool RAG, bool SCL>
 static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
-#if MD_KT == 2
-    if constexpr (tile_kind(PREC_BF16X3, CS, FAST) == 3)
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG, SCL>), dim3(nwg),
+#if MD_KT == 2 || MD_KT == 3
+    constexpr bool H16 = MD_KT == 3;
+    if constexpr (tile_kind(H16 ? PREC_H : PREC_BF16X3, CS, FAST) == 3)
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG, SCL, H16>), dim3(nwg),
                            dim3(Deep<float>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, TileCfg<float>, RAG, SCL>), dim3(nwg),
-                           dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, TileCfg<float>, RAG, SCL, H16>),
+                           dim3(nwg), dim3(NT), 0, s, a);
 #else
     constexpr int kind = tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST);
     if constexpr (kind == 1)

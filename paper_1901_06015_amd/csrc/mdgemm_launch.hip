@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 
+#include "md_half.h"
 #include "md_internal.h"
 
 namespace md {
@@ -19,16 +20,19 @@ namespace md {
 MD_DECL_PARTS(0)
 MD_DECL_PARTS(1)
 MD_DECL_PARTS(2)
+MD_DECL_PARTS(3)
 
 typedef void (*part_fn)(const GemmArgs &, hipStream_t, unsigned);
-// [PREC_S, PREC_D, PREC_BF16X3][case]
-static const part_fn kParts[3][8] = {
+// [PREC_S, PREC_D, PREC_BF16X3, PREC_H][case]
+static const part_fn kParts[4][8] = {
     {launch_part_0_0, launch_part_0_1, launch_part_0_2, launch_part_0_3,
      launch_part_0_4, launch_part_0_5, launch_part_0_6, launch_part_0_7},
     {launch_part_1_0, launch_part_1_1, launch_part_1_2, launch_part_1_3,
      launch_part_1_4, launch_part_1_5, launch_part_1_6, launch_part_1_7},
     {launch_part_2_0, launch_part_2_1, launch_part_2_2, launch_part_2_3,
-     launch_part_2_4, launch_part_2_5, launch_part_2_6, launch_part_2_7}};
+     launch_part_2_4, launch_part_2_5, launch_part_2_6, launch_part_2_7},
+    {launch_part_3_0, launch_part_3_1, launch_part_3_2, launch_part_3_3,
+     launch_part_3_4, launch_part_3_5, launch_part_3_6, launch_part_3_7}};
 
 // C := beta*C (alpha == 0 or k == 0).  beta == 0 writes zeros without reading C.
 __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
@@ -37,7 +41,22 @@ __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = t % g.m, j = t / g.m;
         const int64_t off = i * g.rsc + j * g.ldc;
-        if (g.c_cplx) {
+        if (g.c_half) {
+            // beta is already binary16: products of two binary16 values are
+            // exact in double, their sum nearly always; one rounding to binary16
+            _Float16 *c = (_Float16 *)g.C + (g.c_cplx ? 2 * off : off);
+            const _Float16 *cin = (const _Float16 *)g.Cin + (g.c_cplx ? 2 * off : off);
+            if (g.beta_zero) {
+                c[0] = (_Float16)0.0f;
+                if (g.c_cplx) c[1] = (_Float16)0.0f;
+            } else if (g.c_cplx) {
+                const double br = g.beta_re, bi = g.beta_im, cr = (double)cin[0], ci = (double)cin[1];
+                c[0] = half_rn(br * cr - bi * ci);
+                c[1] = half_rn(br * ci + bi * cr);
+            } else {
+                c[0] = half_rn(g.beta_re * (double)cin[0]);
+            }
+        } else if (g.c_cplx) {
             if (g.c_dbl) {
                 double *c = (double *)g.C + 2 * off;
                 const double *cin = (const double *)g.Cin + 2 * off;
@@ -72,7 +91,7 @@ int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg) 
     const int64_t n = (int64_t)a.tiles_m * a.tiles_n;
     if (wg) *wg = n;
     if (n <= 0) return 0;
-    if (prec < PREC_S || prec > PREC_BF16X3 || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
+    if (prec < PREC_S || prec > PREC_H || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
     kParts[prec][cs](a, (hipStream_t)stream, (unsigned)n);
     return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
 }
@@ -90,17 +109,18 @@ void tile_shape(int prec, int cs, bool fast, int *bm, int *bn, int *bk) {
     const int kind = tile_kind(prec, cs, fast);
     *bm = kind == 2 ? 256 : 128;
     *bn = kind == 1 ? 256 : 128;
-    *bk = prec == PREC_D ? 16 : 32;
+    *bk = prec == PREC_D ? 16 : 32;  // BF16x3 and half: one 16x16x32 step per tile
 }
 
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len) {
     static const char *cases[8] = {"0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3"};
     static const char *tiles[4] = {"t128x128w4", "t128x256w8", "t256x128w8", "t128x128w8"};
     const int kind = tile_kind(prec, cs, a.a_vec && a.b_vec);
-    snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c_%s", prec == PREC_D ? "f64" : (prec == PREC_S ? "f32" : "bf16x3"),
+    snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c_%s",
+             prec == PREC_D ? "f64" : prec == PREC_S ? "f32" : prec == PREC_H ? "f16" : "bf16x3",
              (cs >= 0 && cs < 8) ? cases[cs] : "?",
              (a.a_vec && a.b_vec) ? ((a.a_ragged || a.b_ragged) ? "ragged" : "fast") : "generic",
-             a.a_dbl ? 'd' : 's', a.b_dbl ? 'd' : 's', tiles[kind]);
+             a.a_dbl ? 'd' : (a.a_half ? 'h' : 's'), a.b_dbl ? 'd' : (a.b_half ? 'h' : 's'), tiles[kind]);
 }
 
 }  // namespace md

@@ -7,7 +7,13 @@ import numpy as np
 
 from . import _lib
 
-_DTN = {np.float32: "s", np.float64: "d", np.complex64: "c", np.complex128: "z"}
+_DTN = {np.dtype(np.float32): "s", np.dtype(np.float64): "d", np.dtype(np.complex64): "c",
+        np.dtype(np.complex128): "z", np.dtype(np.float16): "h"}
+
+
+def _dt_name(X):
+    from .inputs import HALF_COMPLEX
+    return "hc" if X.dtype == HALF_COMPLEX else _DTN[X.dtype]
 
 
 class MdServerConfig(ctypes.Structure):
@@ -97,7 +103,7 @@ class Server:
         rows = X.shape[0] if rows is None else rows
         cols = X.shape[1] if cols is None else cols
         h = ctypes.c_int64()
-        st = self.L.md_server_put(self.h, X.ctypes.data, _lib.tag(_DTN[X.dtype.type]), rows, cols, ctypes.byref(h))
+        st = self.L.md_server_put(self.h, X.ctypes.data, _lib.tag(_dt_name(X)), rows, cols, ctypes.byref(h))
         if st != 0:
             raise ServerError(st, "md_server_put")
         return h.value

@@ -15,20 +15,32 @@ import torch
 import oracle
 from paper_1901_06015_amd import _lib, api, inputs
 
-U = {"s": 2.0 ** -24, "d": 2.0 ** -53}
-PREC = {"s": "s", "d": "d", "c": "s", "z": "d"}
+U = {"s": 2.0 ** -24, "d": 2.0 ** -53, "h": 2.0 ** -11}
+PREC = {"s": "s", "d": "d", "c": "s", "z": "d", "h": "h", "hc": "h"}
 SENTINEL = 777.25
 
 
 def to_device(X):
     """Copy a Fortran-ordered host buffer into a device tensor with the same
-    column-major strides."""
+    column-major strides (complex binary16 as torch.complex32)."""
     ld, cols = X.shape
+    if X.dtype == inputs.HALF_COMPLEX:
+        raw = np.ascontiguousarray(X.T).view(np.float16)  # (cols, 2 ld): re, im pairs down each column
+        return torch.from_numpy(raw).to("cuda").view(torch.complex32).t()
     t = torch.empty((max(cols, 1), ld), dtype=api.torch_dtype(
-        {np.float32: "s", np.float64: "d", np.complex64: "c", np.complex128: "z"}[X.dtype.type]),
+        {np.float32: "s", np.float64: "d", np.complex64: "c", np.complex128: "z", np.float16: "h"}[X.dtype.type]),
         device="cuda").t()[:, :cols]
     t.copy_(torch.from_numpy(X))
     return t
+
+
+def to_host(t):
+    """A column-major device tensor back as a Fortran-ordered numpy array of
+    its storage type (complex32 as inputs.HALF_COMPLEX)."""
+    if t.dtype == torch.complex32:
+        raw = t.t().contiguous().view(torch.float16).cpu().numpy()  # (cols, 2 ld)
+        return raw.view(inputs.HALF_COMPLEX).T
+    return t.cpu().numpy()
 
 
 def run(tc, ta, tb, m, n, k, comp="d", transa="N", transb="N", alpha=1.5, beta=-0.5,
@@ -45,7 +57,7 @@ def run(tc, ta, tb, m, n, k, comp="d", transa="N", transb="N", alpha=1.5, beta=-
                      dB.data_ptr(), tb, B.shape[0], beta, dC.data_ptr(), tc, C.shape[0],
                      comp, stream if stream is not None else torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
-    Cout = dC.cpu().numpy()
+    Cout = to_host(dC)
     return st, Cout, dict(A=A, B=B, C=C)
 
 
@@ -120,13 +132,18 @@ def reference(tc, ta, tb, m, n, k, ops, transa="N", transb="N", alpha=1.5, beta=
 
 def bound(tc, comp, k, ref, g, extra=0.0):
     comp = comp.split("+")[0] if isinstance(comp, str) else comp  # "+literal" does not change the precision
-    ux = U[comp if comp in ("s", "d") else ("s" if comp == "bf16x3" else PREC[tc])]
+    comp = comp if comp is not None else PREC[tc]
     uc = U[PREC[tc]]
+    if comp == "h":
+        # operands rounded to binary16 (2 u_h per real product, u_h^2 absorbed),
+        # exact binary16 products, FP32 accumulation
+        return (4.0 * U["h"] + 4.0 * k * U["s"]) * g + 4.0 * uc * np.abs(ref) + extra
+    ux = U["s" if comp == "bf16x3" else comp]
     return 4.0 * k * ux * g + 4.0 * uc * np.abs(ref) + extra
 
 
 def check(tc, comp, k, Cout, m, n, ref, g, extra=0.0, what=""):
-    got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+    got = inputs.to_complex128(np.asarray(Cout[:m, :n]))
     err = np.abs(got - ref)
     b = bound(tc, comp, k, ref, g, extra)
     bad = ~(err <= b)
@@ -142,5 +159,7 @@ def check(tc, comp, k, Cout, m, n, ref, g, extra=0.0, what=""):
 def check_padding(X, rows, what):
     """Rows beyond `rows` (the ld padding) still hold the sentinel."""
     if X.shape[0] > rows:
-        pad = X[rows:, :]
-        assert np.all(pad == SENTINEL), "%s: ld padding was written" % what
+        pad = inputs.to_complex128(X[rows:, :])
+        sentinel = float(np.float16(SENTINEL)) if X.dtype in (np.float16, inputs.HALF_COMPLEX) else SENTINEL
+        want = sentinel * (1 + 1j) if X.dtype == inputs.HALF_COMPLEX else sentinel
+        assert np.all(pad == want), "%s: ld padding was written" % what

@@ -79,6 +79,26 @@ def test_alpha_policy():
             assert st == _lib.MD_ERR_ALPHA_IMAG
 
 
+def test_half_storage_plans():
+    """Binary16 storage (h, hc): the domain case follows the domains, the
+    default computation precision of a half C is half (Section 4.1.1: C's
+    precision), half operands or C take the component-wise kernels, and the
+    half computation precision keeps the fast ones for s/d/c/z storage."""
+    half_tags = ("h", "hc", "s", "z")
+    for tc, ta, tb in itertools.product(half_tags, half_tags, half_tags):
+        st, p = _plan(tc, ta, tb)
+        assert st == 0, (tc, ta, tb, st)
+        want = GOLD[p["case"]]
+        assert (want[1], want[2], want[3]) == (tc in ("hc", "z"), ta in ("hc", "z"), tb in ("hc", "z"))
+        assert p["comp"] == {"h": 3, "hc": 3, "s": 0, "z": 1}[tc]
+        has_half = "h" in (tc, ta, tb) or "hc" in (tc, ta, tb)
+        assert ("_generic_" in p["kernel"]) == has_half, (tc, ta, tb, p["kernel"])
+    st, p = _plan("c", "z", "s", comp="h")
+    assert st == 0 and p["comp"] == 3 and p["kernel"].startswith("md_gemm_f16_") and "_fast_" in p["kernel"]
+    assert _plan("h", "d", "d", ldc=63)[0] == -16
+    assert _plan("hc", "hc", "h", comp="h+literal", alpha=1j)[0] == 0
+
+
 def test_literal_alpha_flag():
     """MD_COMP_LITERAL_ALPHA lifts Section 6.2's refusal of Im(alpha) in the
     six mixed cases; it needs an explicit precision and changes no flop count."""
@@ -130,7 +150,7 @@ def test_argument_errors():
     assert call(dtb=-2) == -11
     assert call(ldb=1) == -12
     assert call(C=None) == -14
-    assert call(dtc=4) == -15
+    assert call(dtc=6) == -15
     assert call(ldc=3) == -16
     assert call(comp=9) == -17
     # lower-case trans letters are accepted; 'C' on real operands equals 'T'
@@ -182,7 +202,7 @@ def test_strided_argument_errors():
     assert call(rsa=1, csa=1, transa="T") == -10   # A stored 2 x 4: columns overlap
     assert call(rsa=3, csa=1, transa="T") == -9    # A stored 2 x 4 by rows: rows overlap below 4
     assert call(B=None) == -11
-    assert call(dtb=5) == -12
+    assert call(dtb=6) == -12
     assert call(rsb=0) == -13
     assert call(csb=1) == -14
     assert call(rsb=2, csb=1) == -13   # B stored by rows: 3 columns need a row stride >= 3

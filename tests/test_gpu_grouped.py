@@ -76,11 +76,11 @@ def check_all(entries, keep, exact=False):
                             A.shape[0], B, e["tb"], B.shape[0], e["beta"], C, e["tc"], C.shape[0],
                             literal_alpha="+literal" in str(e["comp"]))
         assert st == 0
-        Cout = dC.cpu().numpy()
+        Cout = gu.to_host(dC)
         what = "%s%s%s/%s %s%s %dx%dx%d" % (e["tc"], e["ta"], e["tb"], e["comp"], e["transa"], e["transb"],
                                             e["m"], e["n"], e["k"])
         if exact:
-            got = np.asarray(Cout[:e["m"], :e["n"]], dtype=np.complex128)
+            got = inputs.to_complex128(Cout[:e["m"], :e["n"]])
             assert np.array_equal(got, ref), what
         else:
             gu.check(e["tc"], e["comp"], e["k"], Cout, e["m"], e["n"], ref, g, what=what)
@@ -115,6 +115,23 @@ def test_grouped_literal_complex_alpha():
             e["comp"] = e["comp"] + "+literal"
     assert sum("+literal" in e["comp"] for e in entries) >= 8
     say("grouped literal alpha batch of", len(entries))
+    st, keep = run_grouped(entries)
+    assert st == 0, (st, _lib.strerror(st))
+    check_all(entries, keep)
+
+
+def test_grouped_half_precision():
+    """Binary16 storage and the half computation precision inside a grouped
+    call (run on the plain kernels) next to ordinary products, one of them a
+    quick return on a half C."""
+    entries = make_entries(24, seed=23, comps=("s", "d"))
+    halves = (("h", "h", "h", "h"), ("hc", "c", "h", "s"), ("z", "hc", "d", "d"), ("s", "d", "z", "h"),
+              ("hc", "hc", "hc", "h"), ("h", "s", "hc", "s"))
+    for i, (tc, ta, tb, comp) in enumerate(halves):
+        e = entries[3 * i]
+        e.update(tc=tc, ta=ta, tb=tb, comp=comp, alpha=1.5)
+    entries[15]["alpha"] = 0.0
+    say("grouped half batch of", len(entries))
     st, keep = run_grouped(entries)
     assert st == 0, (st, _lib.strerror(st))
     check_all(entries, keep)

@@ -341,6 +341,90 @@ def test_literal_complex_alpha_exact_inputs_bitwise():
                 tc, ta, tb, comp, int((got != ref).sum()))
 
 
+HALF_MIX = [("h", "h", "h"), ("hc", "hc", "hc"), ("s", "h", "h"), ("z", "hc", "d"), ("h", "z", "s"),
+            ("hc", "c", "h"), ("h", "hc", "hc"), ("hc", "h", "z"), ("d", "hc", "h"), ("c", "s", "hc"),
+            ("hc", "d", "s"), ("h", "hc", "z")]
+
+
+@pytest.mark.parametrize("comp", ["s", "d", "h", "bf16x3"])
+def test_half_storage(comp):
+    """Binary16 storage (h, hc) for A, B and C in every domain case, each
+    computation precision, all ops, unaligned leading dimensions; a half C
+    rounds once to binary16 (u_C = 2^-11)."""
+    for i, (tc, ta, tb) in enumerate(HALF_MIX):
+        transa, transb = "NTCR"[i % 4], "RNTC"[(i // 2) % 4]
+        m, n, k = (77, 93, 41) if comp != "bf16x3" else (77, 93, 112)
+        say("half storage %s/%s/%s comp=%s %s%s" % (tc, ta, tb, comp, transa, transb))
+        st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, transa=transa, transb=transb, seed=70 + i,
+                               pad_a=i % 3, pad_b=(i + 1) % 3, pad_c=1)
+        assert st == 0, (st, _lib.strerror(st))
+        ref, g = gu.reference(tc, ta, tb, m, n, k, ops, transa, transb)
+        gu.check(tc, comp, k, Cout, m, n, ref, g, what="half %s/%s/%s/%s" % (tc, ta, tb, comp))
+        gu.check_padding(Cout, m, "C")
+
+
+def test_half_storage_exact_inputs_bitwise():
+    """Integer inputs with half storage anywhere (k = 30 keeps every result
+    exact in binary16): all three computation precisions give the oracle's
+    value bit for bit, through the plain path and a quick return."""
+    for i, (tc, ta, tb) in enumerate(HALF_MIX):
+        for comp in ("s", "d", "h"):
+            say("half exact %s/%s/%s comp=%s" % (tc, ta, tb, comp))
+            m, n, k = 70, 66, 30
+            st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, dist="int", seed=90 + i,
+                                   transa="C" if i % 2 else "N")
+            assert st == 0
+            ref, _ = gu.reference(tc, ta, tb, m, n, k, ops, "C" if i % 2 else "N")
+            got = inputs.to_complex128(Cout[:m, :n])
+            assert np.array_equal(got, ref), "half exact %s/%s/%s/%s: %d mismatches" % (
+                tc, ta, tb, comp, int((got != ref).sum()))
+        st, Cout, ops = gu.run(tc, ta, tb, 20, 10, 0, comp="s", dist="int", seed=3)
+        assert st == 0
+        ref, _ = gu.reference(tc, ta, tb, 20, 10, 0, ops)
+        assert np.array_equal(inputs.to_complex128(Cout[:20, :10]), ref), "half quick return %s/%s/%s" % (tc, ta, tb)
+
+
+@pytest.mark.parametrize("tc", TAGS)
+def test_half_computation_precision(tc):
+    """MD_COMP_H on s/d/c/z storage (the fp16 matrix-core kernels, fast path):
+    every (A, B) pair within the half bound, tiles with ragged edges."""
+    for ta, tb in itertools.product(TAGS, TAGS):
+        for transa, transb, m, n, k in (("N", "N", 150, 140, 70), ("T", "C", 131, 67, 53)):
+            one(tc, ta, tb, m, n, k, "h", transa, transb)
+
+
+def test_half_computation_exact_inputs_bitwise():
+    """Integer inputs are exact in binary16 and every sum is exact in FP32:
+    MD_COMP_H equals the oracle bit for bit on all 64 combinations."""
+    for tc, ta, tb in itertools.product(TAGS, TAGS, TAGS):
+        say("half comp exact %s%s%s" % (tc, ta, tb))
+        m, n, k = 70, 66, 45
+        st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp="h", dist="int", seed=17)
+        assert st == 0
+        ref, _ = gu.reference(tc, ta, tb, m, n, k, ops)
+        got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+        assert np.array_equal(got, ref), "half comp exact %s%s%s: %d mismatches" % (tc, ta, tb, int((got != ref).sum()))
+
+
+def test_half_torch_tensors():
+    """api.gemm on torch.float16 / complex32 tensors (row-major and
+    column-major), the default computation precision of a half C being half."""
+    o = oracle.get()
+    m, n, k = 90, 70, 64
+    XA = inputs.matrix(m, k, "h", 1)
+    XB = inputs.matrix(k, n, "hc", 2)
+    XC = inputs.matrix(m, n, "hc", 3)
+    A = torch.from_numpy(np.ascontiguousarray(XA)).cuda()          # float16, by rows
+    B = gu.to_device(XB)                                            # complex32, by columns
+    C = gu.to_device(XC)
+    say("api.gemm half tensors")
+    api.gemm(A, B, C, alpha=1.5, beta=-0.5)
+    torch.cuda.synchronize()
+    st, ref, g = o.gemm("N", "N", m, n, k, 1.5, XA, "h", m, XB, "hc", k, -0.5, XC, "hc", m)
+    assert st == 0
+    gu.check("hc", "h", k, gu.to_host(C), m, n, ref, g, what="api half tensors")
+
+
 def test_huge_leading_dimension_generic_path():
     """A leading dimension of 2^20 or more keeps the kernels' 32-bit tile
     offsets from fitting: the component-wise path takes over, with the same

@@ -196,3 +196,31 @@ def test_large_requests_take_one_lane_small_ones_pass():
             assert a1 >= d0, "two large requests ran at once"
         assert max(x.t_done_us for x in rs) < rb[-1][1], "small requests waited for every large one"
         assert srv.stats()["completed"] == len(tb) + len(smalls)
+
+
+def test_half_precision_requests():
+    """Binary16 operands, outputs and the half computation precision through
+    the server (small requests batched with ordinary ones): each output
+    matches the oracle."""
+    with Server(budget_bytes=4 << 30, slots=2, max_batch=8, big_flops=2e9) as srv:
+        o = oracle.get()
+        spec = (("h", "h", "h", "h"), ("hc", "c", "hc", "s"), ("z", "hc", "d", "d"), ("s", "s", "s", "h"),
+                ("hc", "hc", "hc", None), ("d", "d", "z", "d"))
+        reqs = []
+        for i, (tc, ta, tb, comp) in enumerate(spec):
+            m, n, k = 40 + 7 * i, 33 + 5 * i, 64
+            A = inputs.matrix(m, k, ta, 300 + 3 * i)
+            B = inputs.matrix(k, n, tb, 301 + 3 * i)
+            C = inputs.matrix(m, n, tc, 302 + 3 * i)
+            r = dict(tc=tc, ta=ta, tb=tb, comp=comp, m=m, n=n, k=k, transa="N", transb="N", alpha=1.5,
+                     beta=-0.5, A=A, B=B, C=C, ha=srv.put(A), hb=srv.put(B), hc=srv.put(C))
+            reqs.append(r)
+        say("serving: half-precision burst of", len(reqs))
+        tickets = [submit(srv, r) for r in reqs]
+        for r, t in zip(reqs, tickets):
+            out, _ = collect(srv, r, t)
+            st, ref, g = o.gemm("N", "N", r["m"], r["n"], r["k"], 1.5, r["A"], r["ta"], r["m"], r["B"], r["tb"],
+                                r["k"], -0.5, r["C"], r["tc"], r["m"])
+            assert st == 0
+            gu.check(r["tc"], r["comp"], r["k"], out, r["m"], r["n"], ref, g,
+                     what="serving half %s/%s/%s/%s" % (r["tc"], r["ta"], r["tb"], r["comp"]))
