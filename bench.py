@@ -204,7 +204,7 @@ def kernel_symbol(plan, transa="N", transb="N"):
     fast, rag = parts[4] in ("fast", "ragged"), parts[4] == "ragged"
     ad, bd = parts[5][0] == "d", parts[5][1] == "d"
     cfg = {"t128x128w4": "TileCfg", "t128x256w8": "WideN", "t256x128w8": "WideM",
-           "t128x128w8": "Deep"}[parts[6]]
+           "t128x128w8": "Deep", "t256x256w8": "Big"}[parts[6]]
     amnc = (transa in "NR") if fast else True
     bmnc = (transb in "TC") if fast else True
     b = lambda v: "true" if v else "false"

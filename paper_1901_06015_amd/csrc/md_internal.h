@@ -81,7 +81,8 @@ enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2, PREC_H = 3 };
 
 // Tile configuration of the plain product kernel for (computation precision,
 // case, fast load path): 0 = 128 x 128 tiles of 4 waves, 1 = 128 x 256 and
-// 2 = 256 x 128 tiles of 8 waves, 3 = 128 x 128 tiles of 8 waves.  The host's
+// 2 = 256 x 128 tiles of 8 waves, 3 = 128 x 128 tiles of 8 waves, 4 = 256 x
+// 256 tiles of 8 waves (half precision only).  The host's
 // tile counts and the device's kernel choice both come from here.  MD_WIDE
 // selects them at build time: bits 0/1 FP64/FP32 -> 128 x 256, bits 2/3 ->
 // 256 x 128, bits 4/5 -> 8-wave 128 x 128.  Default: 8-wave 128 x 128 for
@@ -94,15 +95,17 @@ enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2, PREC_H = 3 };
 #ifndef MD_BF16X3_DEEP
 #define MD_BF16X3_DEEP 0
 #endif
-// MD_H16_DEEP: the half computation precision on the 8-wave 128 x 128 tile
-// (measured 0.82-0.99x the 4-wave tile at 8192).
-#ifndef MD_H16_DEEP
-#define MD_H16_DEEP 0
+// MD_H16_TILE: tile of the half computation precision's fast kernels: 0 the
+// 4-wave 128 x 128 tile, 1 the 8-wave one (measured 0.82-0.99x tile 0 at
+// 8192), 2 (default) the 8-wave 256 x 256 tile (1.23-1.39x tile 0 at 8192:
+// with FP32 or FP64 operands the 128 x 128 tile is bound by operand traffic).
+#ifndef MD_H16_TILE
+#define MD_H16_TILE 2
 #endif
 constexpr int tile_kind(int prec, int cs, bool fast) {
     return !fast ? 0
          : prec == PREC_BF16X3 ? (MD_BF16X3_DEEP ? 3 : 0)
-         : prec == PREC_H ? (MD_H16_DEEP ? 3 : 0)
+         : prec == PREC_H ? (MD_H16_TILE == 2 ? 4 : MD_H16_TILE == 1 ? 3 : 0)
          : (MD_WIDE & (prec == PREC_D ? 1 : 2)) ? 1
          : (MD_WIDE & (prec == PREC_D ? 4 : 8)) ? 2
          : (MD_WIDE & (prec == PREC_D ? 16 : 32)) ? 3 : 0 * cs;

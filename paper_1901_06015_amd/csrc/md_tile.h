@@ -90,6 +90,11 @@ template <> struct WideM<float> : TCfg<float, 256, 128, 32, 2, 4, 2> {};
 template <class T> struct Deep;
 template <> struct Deep<double> : TCfg<double, 128, 128, 16, 4, 2, 4> {};
 template <> struct Deep<float> : TCfg<float, 128, 128, 32, 4, 2, 4> {};
+// 256 x 256 tiles of 8 waves (64 x 128 each): half the operand bytes per
+// flop of a 128 x 128 tile, for the half computation precision, whose
+// one-plane LDS tiles fit (80 KB double-buffered).
+template <class T> struct Big;
+template <> struct Big<float> : TCfg<float, 256, 256, 32, 2, 2, 4> {};
 
 template <class T> struct AccT;
 template <> struct AccT<double> { typedef v4d type; };

@@ -28,7 +28,10 @@ template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, bool RAG, b
 static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 #if MD_KT == 2 || MD_KT == 3
     constexpr bool H16 = MD_KT == 3;
-    if constexpr (tile_kind(H16 ? PREC_H : PREC_BF16X3, CS, FAST) == 3)
+    if constexpr (H16 && tile_kind(PREC_H, CS, FAST) == 4)
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Big<float>, RAG, SCL, H16>), dim3(nwg),
+                           dim3(Big<float>::NT), 0, s, a);
+    else if constexpr (tile_kind(H16 ? PREC_H : PREC_BF16X3, CS, FAST) == 3)
         hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG, SCL, H16>), dim3(nwg),
                            dim3(Deep<float>::NT), 0, s, a);
     else

@@ -107,14 +107,14 @@ int launch_scale(const GemmArgs &a, void *stream) {
 
 void tile_shape(int prec, int cs, bool fast, int *bm, int *bn, int *bk) {
     const int kind = tile_kind(prec, cs, fast);
-    *bm = kind == 2 ? 256 : 128;
-    *bn = kind == 1 ? 256 : 128;
+    *bm = (kind == 2 || kind == 4) ? 256 : 128;
+    *bn = (kind == 1 || kind == 4) ? 256 : 128;
     *bk = prec == PREC_D ? 16 : 32;  // BF16x3 and half: one 16x16x32 step per tile
 }
 
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len) {
     static const char *cases[8] = {"0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3"};
-    static const char *tiles[4] = {"t128x128w4", "t128x256w8", "t256x128w8", "t128x128w8"};
+    static const char *tiles[5] = {"t128x128w4", "t128x256w8", "t256x128w8", "t128x128w8", "t256x256w8"};
     const int kind = tile_kind(prec, cs, a.a_vec && a.b_vec);
     snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c_%s",
              prec == PREC_D ? "f64" : prec == PREC_S ? "f32" : prec == PREC_H ? "f16" : "bf16x3",
