@@ -90,9 +90,10 @@ def gemm(A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", comp=None, stream
     literal_alpha: apply a complex alpha as given in the mixed-domain cases
     (the literal interpretation of Section 6.2) instead of refusing it.
     Returns C."""
-    if literal_alpha:
+    if literal_alpha and not (isinstance(comp, str) and comp.endswith("+literal")):
         if comp is None:
-            comp = "d" if C.dtype in (torch.float64, torch.complex128) else "s"
+            comp = ("d" if C.dtype in (torch.float64, torch.complex128)
+                    else "h" if C.dtype in (torch.float16, torch.complex32) else "s")
         comp = comp + "+literal"
     for t, nm in ((A, "A"), (B, "B"), (C, "C")):
         if not t.is_cuda:
