@@ -208,8 +208,9 @@ def kernel_symbol(plan, transa="N", transb="N"):
     amnc = (transa in "NR") if fast else True
     bmnc = (transb in "TC") if fast else True
     b = lambda v: "true" if v else "false"
-    # the last template argument: alpha staged into an operand (never in the benchmarks)
-    return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s, md::%s<%s>, %s, false>(md::GemmArgs)" % (
+    # the last two template arguments: alpha staged into an operand, binary16
+    # operands (never in the sweep)
+    return "void md::md_gemm_kernel<%s, %d, %s, %s, %s, %s, %s, md::%s<%s>, %s, false, false>(md::GemmArgs)" % (
         t, plan["domain_case"], b(fast), b(ad), b(bd), b(amnc), b(bmnc), cfg, t, b(rag))
 
 

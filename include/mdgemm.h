@@ -42,8 +42,10 @@ typedef enum {
     MD_S = 0, MD_D = 1, MD_C = 2, MD_Z = 3,
     /* Half precision, the next storage precision Section 4's summary names
      * (an addition of this library): IEEE 754 binary16 (MD_H) and complex
-     * binary16 with interleaved re, im (MD_HC).  Operands and C of these
-     * types are served by the component-wise loads and their epilogue. */
+     * binary16 with interleaved re, im (MD_HC).  A half C is written by every
+     * kernel; binary16 A and B together run on the fast loads under the
+     * single and half precisions (each stored column a whole number of
+     * 4-byte words), any other binary16 operand on the component-wise loads. */
     MD_H = 4, MD_HC = 5
 } md_dt;
 

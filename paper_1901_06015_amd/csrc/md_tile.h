@@ -160,8 +160,9 @@ __device__ __forceinline__ int split_pos(int mm, int q) { return (((mm >> 4) << 
 // SCL: the operand is staged as (scale_re + i scale_im) times itself.
 // RTO: double components become float by round-to-odd (float_rto), for the
 // half kernels, which round the staged float once more to binary16.
+// SH (fast path): binary16 storage, 8 components per 16-byte chunk.
 template <class T, int CS, bool IS_A, bool FAST, bool SDBL, bool MNC, class C = TileCfg<T>, bool RAG = false,
-          bool SCL = false, bool RTO = false>
+          bool SCL = false, bool RTO = false, bool SH = false>
 struct Stage {
     static constexpr int MODE = mode_of<CS, IS_A>();
     static constexpr int W = (MODE == M_PLAIN) ? 1 : 2;  // stored components per element
@@ -171,7 +172,7 @@ struct Stage {
     typedef Lay<T, MNC, BMN, C> L;
     static constexpr int TMN = BMN / (MN2 ? 2 : 1);  // stored m (or n) extent of a tile
     static constexpr int TK = C::BK / (K2 ? 2 : 1);   // stored k extent of a tile
-    static constexpr int ESZ = SDBL ? 8 : 4;          // bytes per stored component
+    static constexpr int ESZ = SDBL ? 8 : (SH ? 2 : 4);  // bytes per stored component
     static constexpr int CW = 16 / ESZ;               // components per chunk (one 16-byte load)
     static constexpr int CHUNKS = TMN * TK * W / CW;
     // A tile with fewer chunks than threads (possible with 8 waves) leaves
@@ -183,6 +184,7 @@ struct Stage {
     // realises Re(AB) = ArBr - AiBi; B's Im enters positively.
     static constexpr bool KNEG = IS_A;
     static_assert(FAST || MNC, "the generic path stages into the [k][mn] layout");
+    static_assert(!(SH && (SDBL || !FAST)), "binary16 chunks: fast path, single-width staging");
     static_assert(PARTIAL ? CHUNKS % 64 == 0 : CHUNKS % C::NT == 0, "tile does not split evenly over the workgroup");
     static_assert((TMN * W) % CW == 0 && (TK * W) % CW == 0, "chunks straddle columns");
     static_assert((CPC_MN & (CPC_MN - 1)) == 0 && (CPC_K & (CPC_K - 1)) == 0 && CPC_MN <= C::NT && CPC_K <= C::NT,
@@ -226,7 +228,10 @@ struct Stage {
         col_step = C::NT >> cpc_log;
         active = !PARTIAL || tid < CHUNKS;
         const int64_t rows_st = mn_contig ? MN : K, cols_st = mn_contig ? K : MN;
-        total_bytes = ((cols_st - 1) * ld + rows_st) * W * ESZ;
+        // whole dwords: the buffer range check drops a dword that crosses the
+        // limit, which binary16 data can end inside (the extra bytes share
+        // the last valid element's word; k-contiguous chunks mask them)
+        total_bytes = (((cols_st - 1) * ld + rows_st) * W * ESZ + 3) & ~(int64_t)3;
     }
 
     // FAST path: buffer loads.  A chunk outside the matrix gets an offset
@@ -264,6 +269,15 @@ struct Stage {
                 const int64_t lim = (int64_t)klim * W - pos * CW;
                 if constexpr (SDBL) {
                     if (lim < 2) { v.z = 0u; v.w = 0u; }
+                } else if constexpr (SH) {
+                    // two binary16 components per word, the lower one first
+                    auto keep = [&](uint32_t w, int i) {
+                        return lim <= 2 * i ? 0u : (lim == 2 * i + 1 ? (w & 0xFFFFu) : w);
+                    };
+                    v.x = keep(v.x, 0);
+                    v.y = keep(v.y, 1);
+                    v.z = keep(v.z, 2);
+                    v.w = keep(v.w, 3);
                 } else {
                     if (lim < 2) v.y = 0u;
                     if (lim < 3) v.z = 0u;
@@ -329,6 +343,11 @@ struct Stage {
             const double d = __builtin_bit_cast(double, ((uint64_t)w1 << 32) | w0);
             if constexpr (RTO) return (T)float_rto(d);
             else return (T)d;
+        } else if constexpr (SH) {
+            const int wi = q >> 1;
+            const uint32_t w = wi == 0 ? h.x : (wi == 1 ? h.y : (wi == 2 ? h.z : h.w));
+            const uint16_t b = (q & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xFFFFu);
+            return (T)(float)__builtin_bit_cast(_Float16, b);
         } else {
             const uint32_t w = q == 0 ? h.x : (q == 1 ? h.y : (q == 2 ? h.z : h.w));
             return (T)__builtin_bit_cast(float, w);
@@ -470,14 +489,12 @@ __device__ __forceinline__ void update_real(const GemmArgs &g, int64_t i, int64_
     if (i >= g.m || j >= g.n) return;
     const int64_t off = c_offset<GS>(g, i, j);
     const T ax = (T)g.alpha_re;
-    if constexpr (GS) {
-        if (g.c_half) {
-            // beta is already binary16; the update in double, one rounding to binary16
-            _Float16 *c = (_Float16 *)g.C;
-            const double t = (double)(ax * acc);
-            c[off] = half_rn(g.beta_zero ? t : fma(g.beta_re, (double)((const _Float16 *)g.Cin)[off], t));
-            return;
-        }
+    if (g.c_half) {
+        // beta is already binary16; the update in double, one rounding to binary16
+        _Float16 *c = (_Float16 *)g.C;
+        const double t = (double)(ax * acc);
+        c[off] = half_rn(g.beta_zero ? t : fma(g.beta_re, (double)((const _Float16 *)g.Cin)[off], t));
+        return;
     }
     if (g.c_dbl) {
         double *c = (double *)g.C;
@@ -519,24 +536,22 @@ __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_
     if (i >= g.m || j >= g.n) return;
     const int64_t off = 2 * c_offset<GS>(g, i, j);
     const T ar = (T)g.alpha_re, ai = (T)g.alpha_im;
-    if constexpr (GS) {
-        if (g.c_half) {
-            // alpha*AB in the computation precision, the beta update in double,
-            // one rounding to binary16 per part
-            _Float16 *c = (_Float16 *)g.C + off;
-            const _Float16 *cin = (const _Float16 *)g.Cin + off;
-            const double tr = (double)fma(ar, re, -(ai * im));
-            const double ti = (double)fma(ar, im, ai * re);
-            double rr = tr, ri = ti;
-            if (!g.beta_zero) {
-                const double br = g.beta_re, bi = g.beta_im, cr = (double)cin[0], ci = (double)cin[1];
-                rr = fma(br, cr, fma(-bi, ci, tr));
-                ri = fma(br, ci, fma(bi, cr, ti));
-            }
-            c[0] = half_rn(rr);
-            c[1] = half_rn(ri);
-            return;
+    if (g.c_half) {
+        // alpha*AB in the computation precision, the beta update in double,
+        // one rounding to binary16 per part
+        _Float16 *c = (_Float16 *)g.C + off;
+        const _Float16 *cin = (const _Float16 *)g.Cin + off;
+        const double tr = (double)fma(ar, re, -(ai * im));
+        const double ti = (double)fma(ar, im, ai * re);
+        double rr = tr, ri = ti;
+        if (!g.beta_zero) {
+            const double br = g.beta_re, bi = g.beta_im, cr = (double)cin[0], ci = (double)cin[1];
+            rr = fma(br, cr, fma(-bi, ci, tr));
+            ri = fma(br, ci, fma(bi, cr, ti));
         }
+        c[0] = half_rn(rr);
+        c[1] = half_rn(ri);
+        return;
     }
     if (g.c_dbl) {
         double *c = (double *)g.C + off;
@@ -612,12 +627,13 @@ struct Frag {
 // faster there).
 
 // SCL: the complex operand of case 1a, 2ab (A) or 1b (B) is staged scaled by
-// the complex alpha (GemmArgs::scale_re/scale_im).
+// the complex alpha (GemmArgs::scale_re/scale_im).  SH: A and B are both
+// binary16 (fast path).
 template <class T, int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<T>,
-          bool RAG = false, bool SCL = false>
+          bool RAG = false, bool SCL = false, bool SH = false>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
-    typedef Stage<T, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B> SA;
-    typedef Stage<T, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B> SB;
+    typedef Stage<T, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B, false, SH> SA;
+    typedef Stage<T, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B, false, SH> SB;
     constexpr bool PIPE = C::PIPE;
     constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef typename AccT<T>::type acc_t;

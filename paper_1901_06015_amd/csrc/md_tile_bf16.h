@@ -104,11 +104,11 @@ __device__ __forceinline__ v4f mfma_f16(bf16x8 x, bf16x8 y, v4f c) {
 }
 
 template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<float>, bool RAG = false,
-          bool SCL = false, bool H16 = false>
+          bool SCL = false, bool H16 = false, bool SH = false>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     static_assert(C::BK == 32, "one 16x16x32 step per LDS tile");
-    typedef Stage<float, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B, H16 && AD> SA;
-    typedef Stage<float, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B, H16 && BD> SB;
+    typedef Stage<float, CS, true, FAST, AD, AMNC, C, RAG, SCL && CS != MD_CASE_1B, H16 && AD, SH> SA;
+    typedef Stage<float, CS, false, FAST, BD, BMNC, C, RAG, SCL && CS == MD_CASE_1B, H16 && BD, SH> SB;
     constexpr int WMB = C::WMB, WNB = C::WNB;
     typedef LayBF<AMNC, C::BM> LA;
     typedef LayBF<BMNC, C::BN> LB;

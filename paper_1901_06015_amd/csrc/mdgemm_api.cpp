@@ -158,13 +158,20 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     // They address a tile with 32-bit offsets from its origin: 128 columns of
     // the operand must span less than 2 GiB.
     const int wa = dt_cplx(dta) ? 2 : 1, wb = dt_cplx(dtb) ? 2 : 1;
-    const int cwa = dt_dbl(dta) ? 2 : 4, cwb = dt_dbl(dtb) ? 2 : 4;  // components per chunk
+    // components per 16-byte chunk
+    const int cwa = dt_dbl(dta) ? 2 : (dt_half(dta) ? 8 : 4), cwb = dt_dbl(dtb) ? 2 : (dt_half(dtb) ? 8 : 4);
     const int64_t max_ld = ((int64_t)1 << 31) / (128 * 16) - 64;
-    // General storage (an element stride along the column, for any operand) and
-    // half-precision storage (any operand or C) take the component-wise path.
-    const bool plain_c = rsc == 1 && !dt_half(dtc);
-    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld && rsa == 1 && plain_c && !dt_half(dta);
-    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld && rsb == 1 && plain_c && !dt_half(dtb);
+    // General storage (an element stride along the column, for any operand)
+    // takes the component-wise path.  Binary16 operands have fast kernels when
+    // both A and B are binary16 and the precision is single or half, with
+    // every stored column a whole number of 4-byte words; otherwise they take
+    // the component-wise path too.
+    const bool plain_c = rsc == 1;
+    const bool half_pair = dt_half(dta) && dt_half(dtb) && (d.prec == PREC_S || d.prec == PREC_H) &&
+                           (lda * wa) % 2 == 0 && (ldb * wb) % 2 == 0;
+    const bool ha_ok = !dt_half(dta) || half_pair, hb_ok = !dt_half(dtb) || half_pair;
+    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld && rsa == 1 && plain_c && ha_ok;
+    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld && rsb == 1 && plain_c && hb_ok;
     g.a_ragged = (ta == 1 || ta == 2) && (k * wa) % cwa != 0;
     g.b_ragged = (tb == 0 || tb == 3) && (k * wb) % cwb != 0;
     g.alpha_re = are; g.alpha_im = aim;

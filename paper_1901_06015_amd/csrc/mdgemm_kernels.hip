@@ -24,38 +24,47 @@ typedef double KT;
 typedef float KT;
 #endif
 
-template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, bool RAG, bool SCL>
+template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, bool RAG, bool SCL, bool SH = false>
 static void launch_k(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 #if MD_KT == 2 || MD_KT == 3
     constexpr bool H16 = MD_KT == 3;
     if constexpr (H16 && tile_kind(PREC_H, CS, FAST) == 4)
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Big<float>, RAG, SCL, H16>), dim3(nwg),
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Big<float>, RAG, SCL, H16, SH>), dim3(nwg),
                            dim3(Big<float>::NT), 0, s, a);
     else if constexpr (tile_kind(H16 ? PREC_H : PREC_BF16X3, CS, FAST) == 3)
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG, SCL, H16>), dim3(nwg),
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, Deep<float>, RAG, SCL, H16, SH>), dim3(nwg),
                            dim3(Deep<float>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, TileCfg<float>, RAG, SCL, H16>),
+        hipLaunchKernelGGL((md_bf16x3_kernel<CS, FAST, AD, BD, AMNC, BMNC, TileCfg<float>, RAG, SCL, H16, SH>),
                            dim3(nwg), dim3(NT), 0, s, a);
 #else
     constexpr int kind = tile_kind(MD_KT == 1 ? PREC_D : PREC_S, CS, FAST);
     if constexpr (kind == 1)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideN<KT>, RAG, SCL>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideN<KT>, RAG, SCL, SH>), dim3(nwg),
                            dim3(WideN<KT>::NT), 0, s, a);
     else if constexpr (kind == 2)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideM<KT>, RAG, SCL>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, WideM<KT>, RAG, SCL, SH>), dim3(nwg),
                            dim3(WideM<KT>::NT), 0, s, a);
     else if constexpr (kind == 3)
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, Deep<KT>, RAG, SCL>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, Deep<KT>, RAG, SCL, SH>), dim3(nwg),
                            dim3(Deep<KT>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, TileCfg<KT>, RAG, SCL>), dim3(nwg),
+        hipLaunchKernelGGL((md_gemm_kernel<KT, CS, FAST, AD, BD, AMNC, BMNC, TileCfg<KT>, RAG, SCL, SH>), dim3(nwg),
                            dim3(NT), 0, s, a);
 #endif
 }
 
 template <int CS, bool FAST, bool AMNC, bool BMNC, bool RAG, bool SCL>
 static void launch_v(const GemmArgs &a, hipStream_t s, unsigned nwg) {
+#if MD_KT == 0 || MD_KT == 3
+    // binary16 A and B on the fast path (single and half precision only)
+    if constexpr (FAST) {
+        if (a.a_half) {
+            launch_k<CS, FAST, false, false, AMNC, BMNC, RAG, SCL, true>(a, s, nwg);
+            return;
+        }
+    }
+#endif
     if (a.a_dbl) {
         if (a.b_dbl) launch_k<CS, FAST, true, true, AMNC, BMNC, RAG, SCL>(a, s, nwg);
         else launch_k<CS, FAST, true, false, AMNC, BMNC, RAG, SCL>(a, s, nwg);

@@ -82,8 +82,9 @@ def test_alpha_policy():
 def test_half_storage_plans():
     """Binary16 storage (h, hc): the domain case follows the domains, the
     default computation precision of a half C is half (Section 4.1.1: C's
-    precision), half operands or C take the component-wise kernels, and the
-    half computation precision keeps the fast ones for s/d/c/z storage."""
+    precision); a half C takes the fast kernels, binary16 operands take them
+    when both are binary16 and the precision is single or half, and the half
+    computation precision keeps them for s/d/c/z storage."""
     half_tags = ("h", "hc", "s", "z")
     for tc, ta, tb in itertools.product(half_tags, half_tags, half_tags):
         st, p = _plan(tc, ta, tb)
@@ -91,11 +92,16 @@ def test_half_storage_plans():
         want = GOLD[p["case"]]
         assert (want[1], want[2], want[3]) == (tc in ("hc", "z"), ta in ("hc", "z"), tb in ("hc", "z"))
         assert p["comp"] == {"h": 3, "hc": 3, "s": 0, "z": 1}[tc]
-        has_half = "h" in (tc, ta, tb) or "hc" in (tc, ta, tb)
-        assert ("_generic_" in p["kernel"]) == has_half, (tc, ta, tb, p["kernel"])
+        a_h, b_h = ta in ("h", "hc"), tb in ("h", "hc")
+        fast = (not a_h and not b_h) or (a_h and b_h and p["comp"] in (0, 3))
+        assert ("_fast_" in p["kernel"]) == fast, (tc, ta, tb, p["kernel"])
     st, p = _plan("c", "z", "s", comp="h")
     assert st == 0 and p["comp"] == 3 and p["kernel"].startswith("md_gemm_f16_") and "_fast_" in p["kernel"]
     assert _plan("h", "d", "d", ldc=63)[0] == -16
+    # an odd leading dimension of a real binary16 operand leaves columns off
+    # 4-byte boundaries: component-wise loads
+    assert "_generic_" in _plan("h", "h", "h", m=63, lda=63)[1]["kernel"]
+    assert "_fast_" in _plan("h", "h", "h", m=64)[1]["kernel"]
     assert _plan("hc", "hc", "h", comp="h+literal", alpha=1j)[0] == 0
 
 

@@ -406,6 +406,38 @@ def test_half_computation_exact_inputs_bitwise():
         assert np.array_equal(got, ref), "half comp exact %s%s%s: %d mismatches" % (tc, ta, tb, int((got != ref).sum()))
 
 
+@pytest.mark.parametrize("comp", ["s", "h"])
+def test_half_fast_path(comp):
+    """Binary16 A and B on the 16-byte fast loads (single and half precision):
+    every op pair, ragged k (chunks of 8 binary16 components), tile edges,
+    half and wider C; the plan confirms the fast or ragged kernel."""
+    combos = [("h", "h", "h"), ("s", "h", "h"), ("hc", "hc", "hc"), ("z", "h", "hc"), ("c", "hc", "h"),
+              ("h", "h", "hc"), ("hc", "hc", "h"), ("d", "hc", "hc")]
+    for i, (tc, ta, tb) in enumerate(combos):
+        for transa, transb in (("N", "N"), ("T", "C"), ("R", "T"), ("C", "R")):
+            m, n, k = (150, 140, 70) if i % 2 == 0 else (98, 131, 41)
+            ar = m if transa in "NR" else k
+            br = k if transb in "NR" else n
+            pad_a, pad_b = ar % 2, br % 2 + 2    # whole 4-byte words per stored column
+            st, pl = _lib.mdgemm_plan(transa, transb, m, n, k, 1.5, 0x1000, ta, ar + pad_a, 0x1000, tb, br + pad_b,
+                                      -0.5, 0x1000, tc, m + 1, comp)
+            assert st == 0 and ("_fast_" in pl["kernel"] or "_ragged_" in pl["kernel"]), pl["kernel"]
+            one(tc, ta, tb, m, n, k, comp, transa, transb, pad_a=pad_a, pad_b=pad_b, pad_c=1)
+
+
+def test_half_fast_path_exact_inputs_bitwise():
+    """Integer inputs through the binary16 fast loads: bit for bit."""
+    for tc, ta, tb in (("h", "h", "h"), ("s", "h", "h"), ("hc", "hc", "hc"), ("z", "hc", "h")):
+        for comp in ("s", "h"):
+            say("half fast exact %s/%s/%s comp=%s" % (tc, ta, tb, comp))
+            m, n, k = 70, 66, 30
+            st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, dist="int", seed=29, transa="T", transb="C")
+            assert st == 0
+            ref, _ = gu.reference(tc, ta, tb, m, n, k, ops, "T", "C")
+            got = inputs.to_complex128(Cout[:m, :n])
+            assert np.array_equal(got, ref), "half fast exact %s/%s/%s/%s" % (tc, ta, tb, comp)
+
+
 def test_half_torch_tensors():
     """api.gemm on torch.float16 / complex32 tensors (row-major and
     column-major), the default computation precision of a half C being half."""
