@@ -65,10 +65,10 @@ def parse():
     p.add_argument("--big-lanes", type=int, default=2, help="serving: large requests running at once")
     p.add_argument("--no-plain-stream", action="store_true",
                    help="serving: skip the plain-form run of the same arrival stream")
-    p.add_argument("--workload", default="sweep", choices=["sweep", "precision", "grouped", "serving"],
+    p.add_argument("--workload", default="sweep", choices=["sweep", "precision", "grouped", "serving", "single"],
                    help="sweep: the 128-combination plain method at 4096 (default); precision: "
                         "FP32 vs BF16x3 at 8192; grouped: 512 mixed GEMMs in one launch; serving: "
-                        "Poisson request stream")
+                        "Poisson request stream; single: one zcdd product at 256 (latency)")
     return p.parse_args()
 
 
@@ -366,6 +366,110 @@ def precision_workload(args):
                          "bf16_mfma_utilisation": round(3 * agg["bf16x3"] / 2.5e6, 4),
                          "f16_mfma_utilisation": round(agg["h"] / 2.5e6, 4)},
             "per_combo": out}
+    print(json.dumps(line), flush=True)
+
+
+def single_workload(args):
+    """One mixed product, zcdd (case 2ac) at m=n=k=256, alpha = beta = 1,
+    double precision: a latency-bound call.  Device time per call (HIP events
+    on the call's stream) and host wall time per call (enqueue to
+    completion), p50/p99 over 2000 calls; beside them the vendor dgemm at the
+    lowered real shape 512 x 256 x 256 and at 256^3; the result checked in
+    full against the oracle."""
+    import torch
+    import oracle
+    from paper_1901_06015_amd import _lib, inputs
+    n, reps = 256, 2000
+    A = inputs.matrix(n, n, "c", 11)
+    B = inputs.matrix(n, n, "d", 12)
+    C0 = inputs.matrix(n, n, "z", 13)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.from_numpy(C0).cuda()
+    s = torch.cuda.current_stream()
+    sp = s.cuda_stream
+    call = lambda: _lib.mdgemm("N", "N", n, n, n, 1.0, dA.data_ptr(), "c", n, dB.data_ptr(), "d", n, 1.0,
+                               dC.data_ptr(), "z", n, "d", sp)
+    assert call() == 0
+    torch.cuda.synchronize()
+    dC.copy_(torch.from_numpy(C0))
+    assert call() == 0
+    torch.cuda.synchronize()
+    st, ref, g = oracle.get().gemm("N", "N", n, n, n, 1.0, A, "c", n, B, "d", n, 1.0, C0, "z", n)
+    assert st == 0
+    got = dC.cpu().numpy()
+    bound = 4 * n * 2.0 ** -53 * g + 4 * 2.0 ** -53 * np.abs(ref)
+    ratio = float(np.max(np.abs(got - ref) / bound))
+    assert ratio <= 1.0, "single: outside the bound (%.3g)" % ratio
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(s)
+        call()
+        e1.record(s)
+    torch.cuda.synchronize()
+    dev = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])  # us
+    wall = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e6)
+    wall = np.array(wall)
+
+    def native(m_, n_, k_):
+        a = torch.rand(m_, k_, dtype=torch.float64, device="cuda")
+        b = torch.rand(k_, n_, dtype=torch.float64, device="cuda")
+        c = torch.empty(m_, n_, dtype=torch.float64, device="cuda")
+        for _ in range(20):
+            torch.matmul(a, b, out=c)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record()
+            torch.matmul(a, b, out=c)
+            e1.record()
+        torch.cuda.synchronize()
+        t = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in evs])
+        return {"p50_us": round(float(np.median(t)), 2), "p99_us": round(float(np.percentile(t, 99)), 2),
+                "gflops": round(2.0 * m_ * n_ * k_ / (np.median(t) * 1e-6) / 1e9, 1)}
+
+    # the same product as a one-descriptor grouped launch (64-wide tiles: more
+    # workgroups for a small product)
+    desc = [_lib.make_desc("N", "N", n, n, n, 1.0, dA.data_ptr(), "c", n, dB.data_ptr(), "d", n, 1.0,
+                           dC.data_ptr(), "z", n, "d")]
+    for _ in range(20):
+        assert _lib.mdgemm_grouped(desc, sp) == 0
+    torch.cuda.synchronize()
+    evg = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evg:
+        e0.record(s)
+        _lib.mdgemm_grouped(desc, sp)
+        e1.record(s)
+    torch.cuda.synchronize()
+    grp = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in evg])
+    dC.copy_(torch.from_numpy(C0))
+    assert _lib.mdgemm_grouped(desc, sp) == 0
+    torch.cuda.synchronize()
+    gratio = float(np.max(np.abs(dC.cpu().numpy() - ref) / bound))
+    assert gratio <= 1.0, "single (grouped): outside the bound (%.3g)" % gratio
+
+    flops = 4.0 * n ** 3
+    nbytes = n * n * (8 + 8 + 16 + 16)  # A (c), B (d), C read and written (z)
+    p50 = float(np.median(dev))
+    t_floor = max(flops / 78.6e12, nbytes / 8e12) * 1e6
+    line = {"metric": "latency of one mixed GEMM (zcdd, m=n=k=256, double)", "value": round(p50, 2),
+            "unit": "us", "n_gpus": 1, "steps": reps, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "single product zcdd (case 2ac) m=n=k=256 column-major, alpha=1, beta=1, "
+                                   "computation precision double, U[-1,1]"},
+            "device_us": {"p50": round(p50, 2), "p99": round(float(np.percentile(dev, 99)), 2)},
+            "host_wall_us": {"p50": round(float(np.median(wall)), 2), "p99": round(float(np.percentile(wall, 99)), 2)},
+            "gflops": round(flops / (p50 * 1e-6) / 1e9, 1),
+            "roofline": {"bound": "latency", "floor_us": round(t_floor, 3),
+                         "note": "max(4mnk / FP64 MFMA peak, algorithmic bytes / 8 TB/s)",
+                         "frac": round(t_floor / p50, 4)},
+            "grouped_one_descriptor_us": {"p50": round(float(np.median(grp)), 2),
+                                          "p99": round(float(np.percentile(grp, 99)), 2)},
+            "native_dgemm": {"512x256x256": native(2 * n, n, n), "256x256x256": native(n, n, n)},
+            "oracle_max_err_over_bound": ratio}
     print(json.dumps(line), flush=True)
 
 
@@ -763,6 +867,8 @@ def main():
         return grouped_workload(args)
     if args.workload == "serving":
         return serving_workload(args)
+    if args.workload == "single":
+        return single_workload(args)
     import torch
     from paper_1901_06015_amd import _lib, api
     _lib.lib()
