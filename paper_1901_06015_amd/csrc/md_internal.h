@@ -75,6 +75,9 @@ struct GemmArgs {
     int a_scale, b_scale;       // stage A (B) as (scale_re + i scale_im) times itself: a complex
     double scale_re, scale_im;  // alpha under the literal interpretation with C real
     int tiles_m, tiles_n;     // workgroup tiles of the real product
+    int splits;               // > 1: k split over this many workgroups per tile (plain kernels)
+    void *part;               // their partial products: splits x n x m pairs (re, im) of the
+                              // computation type, summed and finished by md_split_reduce
 };
 
 enum Prec { PREC_S = 0, PREC_D = 1, PREC_BF16X3 = 2, PREC_H = 3 };

@@ -477,6 +477,16 @@ __device__ __forceinline__ void map_tile(int wg, int nwg, int tiles_m, int tiles
 // ---------------------------------------------------------------------------
 // Epilogue: C := beta*C + alpha*AB, rounded once to C's storage type
 // ---------------------------------------------------------------------------
+// Partial product of split workgroup `split` for C(i, j): alpha-free (re, im)
+// in the computation type, at part[split][j][i].
+template <class T>
+__device__ __forceinline__ void store_partial(const GemmArgs &g, int split, int64_t i, int64_t j, T re, T im) {
+    if (i >= g.m || j >= g.n) return;
+    T *p = (T *)g.part + 2 * (((int64_t)split * g.n + j) * g.m + i);
+    p[0] = re;
+    p[1] = im;
+}
+
 // GS: C may have an element stride along its columns (general storage; only
 // the component-wise kernels are launched for it).
 template <bool GS>
@@ -646,10 +656,16 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave % C::WGM) * (C::BM / C::WGM), wn0 = (wave / C::WGM) * (C::BN / C::WGN);
+    // With g.splits > 1 the workgroups of one tile take consecutive ranges of
+    // its k-tiles and store their partial products (md_split_reduce finishes).
+    const int nsplit = g.splits > 1 ? g.splits : 1;
+    const int split = (int)(blockIdx.x % nsplit);
     int tm, tn;
-    map_tile(blockIdx.x, gridDim.x, g.tiles_m, g.tiles_n, &tm, &tn);
+    map_tile(blockIdx.x / nsplit, gridDim.x / nsplit, g.tiles_m, g.tiles_n, &tm, &tn);
     const int64_t mn0a = (int64_t)tm * SA::TMN, mn0b = (int64_t)tn * SB::TMN;
-    const int nk = (int)((g.k + SA::TK - 1) / SA::TK);
+    const int nk_all = (int)((g.k + SA::TK - 1) / SA::TK);
+    const int t0 = (int)((int64_t)nk_all * split / nsplit);
+    const int nk = (int)((int64_t)nk_all * (split + 1) / nsplit) - t0;
 
     acc_t acc[WMB][WNB];
 #pragma unroll
@@ -675,8 +691,8 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                 la.store(sA[cur ^ 1]);
                 lb.store(sB[cur ^ 1]);
                 if (next_load < nk) {
-                    la.load(next_load);
-                    lb.load(next_load);
+                    la.load(t0 + next_load);
+                    lb.load(t0 + next_load);
                 }
             }
             if (s + 1 < S) {
@@ -694,14 +710,14 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
         }
     };
 
-    la.load(0);
-    lb.load(0);
+    la.load(t0);
+    lb.load(t0);
     la.store(sA[0]);
     lb.store(sB[0]);
     __syncthreads();
     if (nk > 1) {
-        la.load(1);
-        lb.load(1);
+        la.load(t0 + 1);
+        lb.load(t0 + 1);
     }
     fa.read(sA[0], 0, lane, wm0);
     fb.read(sB[0], 0, lane, wn0);
@@ -711,8 +727,8 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
         tile(cur, std::true_type{}, t + 2);
         __syncthreads();
         if (!PIPE && t + 2 < nk) {
-            la.load(t + 2);
-            lb.load(t + 2);
+            la.load(t0 + t + 2);
+            lb.load(t0 + t + 2);
         }
         fa.read(sA[cur ^ 1], 0, lane, wm0);
         fb.read(sB[cur ^ 1], 0, lane, wn0);
@@ -721,6 +737,15 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
 
     // Epilogue.  acc[a][b] item v is C'(row m = wm0 + 16a + (lane & 15),
     //                                   col n = wn0 + 16b + acc_row(lane, v)).
+    // A split workgroup stores its partial (re, im) instead.
+    auto put_cplx = [&](int64_t i, int64_t j, T re, T im) {
+        if (nsplit > 1) store_partial(g, split, i, j, re, im);
+        else update_cplx<T, !FAST>(g, i, j, re, im);
+    };
+    auto put_real = [&](int64_t i, int64_t j, T re) {
+        if (nsplit > 1) store_partial(g, split, i, j, re, (T)0);
+        else update_real<T, !FAST>(g, i, j, re);
+    };
     const int ml = lane & 15;
 #pragma unroll
     for (int b = 0; b < WNB; ++b) {
@@ -732,7 +757,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                 for (int q = 0; q < WMB / 2; ++q) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    update_cplx<T, !FAST>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
+                    put_cplx(i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
                 }
             } else if constexpr (NDBL) {
                 if ((b & 1) == 0) {
@@ -740,7 +765,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                     for (int a = 0; a < WMB; ++a) {
                         const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                         const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
-                        update_cplx<T, !FAST>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
+                        put_cplx(i, j, acc[a][b][v], acc[a][b + 1][v]);
                     }
                 }
             } else {
@@ -748,8 +773,8 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                 for (int a = 0; a < WMB; ++a) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    if constexpr (CCPLX) update_cplx<T, !FAST>(g, i, j, acc[a][b][v], (T)0);
-                    else update_real<T, !FAST>(g, i, j, acc[a][b][v]);
+                    if constexpr (CCPLX) put_cplx(i, j, acc[a][b][v], (T)0);
+                    else put_real(i, j, acc[a][b][v]);
                 }
             }
         }

@@ -1,10 +1,14 @@
 // mdgemm_launch.hip -- host-side dispatch to the product kernels, the
 // beta-scaling kernel used by the quick returns, and tile/kernel metadata.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 #include <stdio.h>
+
+#include <mutex>
 
 #include "md_half.h"
 #include "md_internal.h"
+#include "md_tile.h"
 
 namespace md {
 
@@ -87,12 +91,111 @@ __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
 }
 
 
-int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg) {
-    const int64_t n = (int64_t)a.tiles_m * a.tiles_n;
+// Sum of the split partial products of C(i, j) in split order, then the
+// epilogue of the unsplit kernels (alpha, beta, one rounding to C's type).
+template <class T>
+__global__ __launch_bounds__(256) void md_split_reduce(GemmArgs g) {
+    const int64_t total = g.m * g.n, stride = 2 * total;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t % g.m, j = t / g.m;
+        const T *p = (const T *)g.part + 2 * t;
+        T re = 0, im = 0;
+        for (int s = 0; s < g.splits; ++s) {
+            re += p[s * stride];
+            im += p[s * stride + 1];
+        }
+        if (g.c_cplx) update_cplx<T, true>(g, i, j, re, im);
+        else update_real<T, true>(g, i, j, re);
+    }
+}
+
+static int g_cu_count = 0;
+static int cu_count() {
+    if (g_cu_count == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        g_cu_count = v;
+    }
+    return g_cu_count;
+}
+
+// k split for the FP32/FP64 kernels when the tiles cannot fill the device:
+// fewer tiles than half the CUs, at least 4 k-tiles per split (2: measured
+// slower at 256), at most 16.
+static int split_count(int prec, int cs, const GemmArgs &a, int64_t tiles) {
+    if (prec != PREC_S && prec != PREC_D) return 1;
+    const int cus = cu_count();
+    if (tiles * 2 > cus) return 1;
+    int bm, bn, bk;
+    tile_shape(prec, cs, a.a_vec && a.b_vec, &bm, &bn, &bk);
+    const int64_t k_real = a.k * (lower_case(cs).kdbl ? 2 : 1);
+    const int64_t nk = (k_real + bk - 1) / bk;
+    int64_t s = (cus + tiles - 1) / tiles;
+    if (s > nk / 4) s = nk / 4;
+    if (s > 16) s = 16;
+    return s > 1 ? (int)s : 1;
+}
+
+// The split workspaces come from a stream-ordered pool of the library's own
+// (one per device, created on first use) that keeps freed memory for reuse,
+// so an allocation after a synchronisation does not go back to the driver.
+static std::mutex g_pool_mu;
+static hipMemPool_t g_pools[64];
+static bool g_pool_tried[64];
+static hipMemPool_t split_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool_tried[dev]) {
+        g_pool_tried[dev] = true;
+        hipMemPoolProps props = {};
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t p = nullptr;
+        if (hipMemPoolCreate(&p, &props) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+            g_pools[dev] = p;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    return g_pools[dev];
+}
+
+int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg) {
+    const int64_t n = (int64_t)a0.tiles_m * a0.tiles_n;
     if (wg) *wg = n;
     if (n <= 0) return 0;
     if (prec < PREC_S || prec > PREC_H || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
-    kParts[prec][cs](a, (hipStream_t)stream, (unsigned)n);
+    hipStream_t s = (hipStream_t)stream;
+    GemmArgs a = a0;
+    a.splits = split_count(prec, cs, a0, n);
+    a.part = nullptr;
+    if (a.splits > 1) {
+        const size_t esz = prec == PREC_D ? sizeof(double) : sizeof(float);
+        const size_t bytes = (size_t)a.splits * (size_t)a.m * (size_t)a.n * 2 * esz;
+        // stream-ordered workspace; without it the product runs unsplit
+        hipMemPool_t pool = split_pool();
+        if (!pool || hipMallocFromPoolAsync(&a.part, bytes, pool, s) != hipSuccess) {
+            (void)hipGetLastError();
+            a.part = nullptr;
+            a.splits = 1;
+        }
+    }
+    kParts[prec][cs](a, s, (unsigned)(n * a.splits));
+    if (a.splits > 1) {
+        const int64_t total = a.m * a.n;
+        int64_t blocks = (total + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        if (prec == PREC_D) hipLaunchKernelGGL(md_split_reduce<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(md_split_reduce<float>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        (void)hipFreeAsync(a.part, s);
+    }
     return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
 }
 

@@ -457,6 +457,40 @@ def test_half_torch_tensors():
     gu.check("hc", "h", k, gu.to_host(C), m, n, ref, g, what="api half tensors")
 
 
+@pytest.mark.parametrize("comp", ["s", "d"])
+def test_split_k_small_tiles(comp):
+    """Products with few tiles and a deep k split k over several workgroups
+    (partials in the computation type, summed in split order, one epilogue):
+    every domain case, fast and component-wise loads, ragged k, a half C."""
+    combos = ["ddd", "sdc", "dzs", "scz", "csd", "zdz", "czs", "zcz", "hss", "hcz"]
+    for i, cab in enumerate(combos):
+        tc, ta, tb = (cab[0], cab[1], cab[2]) if cab[0] != "h" else (("h", "s", "s") if i == 8 else ("hc", "c", "z"))
+        m, n, k = (100, 90, 2000) if i % 2 == 0 else (70, 130, 1531)
+        pad = 1 if i % 3 == 2 else 0
+        st, pl = _lib.mdgemm_plan("T" if i % 4 == 1 else "N", "N", m, n, k, 1.5, 0x1000, ta,
+                                  k if i % 4 == 1 else m + pad, 0x1000, tb, k, -0.5, 0x1000, tc, m, comp)
+        assert st == 0 and pl["workgroups"] * 2 <= 256, pl
+        one(tc, ta, tb, m, n, k, comp, "T" if i % 4 == 1 else "N", "N", pad_a=0 if i % 4 == 1 else pad)
+
+
+def test_split_k_exact_and_strided():
+    """Split k on integer inputs gives the oracle bit for bit; a general-stride
+    and a row-major C through the split path stay within the bound."""
+    for tc, ta, tb, comp in (("z", "c", "d", "d"), ("s", "s", "s", "s"), ("c", "z", "z", "s"), ("d", "d", "c", "d")):
+        say("split exact %s%s%s/%s" % (tc, ta, tb, comp))
+        m, n, k = 64, 96, 1024
+        st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, dist="int", seed=5)
+        assert st == 0
+        ref, _ = gu.reference(tc, ta, tb, m, n, k, ops)
+        got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+        assert np.array_equal(got, ref), "split exact %s%s%s/%s" % (tc, ta, tb, comp)
+    for layouts in (("col", "col", "gen"), ("row", "col", "row")):
+        say("split strided", layouts)
+        st, got, pad_ok, ref, g = gu.run_strided("z", "c", "d", 60, 50, 1200, layouts, "d", "N", "T", seed=3)
+        assert st == 0 and pad_ok
+        gu.check("z", "d", 1200, got, 60, 50, ref, g, what="split strided %s" % (layouts,))
+
+
 def test_huge_leading_dimension_generic_path():
     """A leading dimension of 2^20 or more keeps the kernels' 32-bit tile
     offsets from fitting: the component-wise path takes over, with the same
