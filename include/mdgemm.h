@@ -4,26 +4,32 @@
  *     C := beta*C + alpha*op(A)*op(B)
  *
  * where each of A, B and C is independently stored as single or double
- * precision, real or complex (s, d, c, z) and the computation precision is
- * chosen separately from the storage precisions.  The operation and the three
- * op() variants are those of the BLAS gemm (Van Zee, Parikh, van de Geijn,
- * "Supporting mixed-datatype matrix multiplication within the BLIS framework",
- * Section 1); the domain of the computation follows from which operands are
- * complex (Section 3.2, Figure "mixeddom"); the computation precision and the
- * target types of A and B follow Section 4.1; the scalar policies follow
- * Section 6.
+ * precision, real or complex (s, d, c, z; and binary16 h, hc, an addition)
+ * and the computation precision is chosen separately from the storage
+ * precisions.  The operation and the three op() variants are those of the
+ * BLAS gemm (Van Zee, Parikh, van de Geijn, "Supporting mixed-datatype matrix
+ * multiplication within the BLIS framework", Section 1), plus conjugation
+ * without transposition ('R', Section 2); the domain of the computation
+ * follows from which operands are complex (Section 3.2, Figure "mixeddom");
+ * the computation precision and the target types of A and B follow Section
+ * 4.1; the scalar policies follow Section 6.
  *
- * Storage conventions (all entry points):
+ * Storage conventions (all entry points but mdgemm_strided, which takes row
+ * and column strides):
  *   - matrices are column-major; complex elements are interleaved (re, im);
  *   - a leading dimension counts elements of that operand's own type and must
- *     be >= max(1, rows) of the stored matrix (rows of A are m for transa 'N',
- *     else k; rows of B are k for transb 'N', else n; rows of C are m);
+ *     be >= max(1, rows) of the stored matrix (rows of A are m for transa 'N'
+ *     or 'R', else k; rows of B are k for transb 'N' or 'R', else n; rows of
+ *     C are m);
  *   - A, B and C are device pointers owned by the caller; A and B are only
  *     read; C is updated in place and must not overlap A or B (A may equal B);
  *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
  *     the call returns before it completes: the caller keeps every buffer alive
  *     until the stream has finished;
- *   - on any error return nothing is enqueued and C is unmodified.
+ *   - on any error return nothing is enqueued and C is unmodified;
+ *   - a product with few output tiles and a deep k may take a workspace for
+ *     its split-k partial products from the library's own stream-ordered
+ *     memory pool (released to the pool on the same stream).
  *
  * Return codes: 0 on success; -i when argument i (1-based, in mdgemm's order)
  * is invalid; positive MD_ERR_* codes otherwise (see mdgemm_strerror).
