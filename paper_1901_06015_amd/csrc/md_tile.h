@@ -494,12 +494,14 @@ __device__ __forceinline__ int64_t c_offset(const GemmArgs &g, int64_t i, int64_
     return (GS ? i * g.rsc : i) + j * g.ldc;
 }
 
-template <class T, bool GS = false>
+// HC: C may be binary16 (the plain kernels and the split reduction; the
+// grouped kernel, which never sees one, leaves that code out).
+template <class T, bool GS = false, bool HC = false>
 __device__ __forceinline__ void update_real(const GemmArgs &g, int64_t i, int64_t j, T acc) {
     if (i >= g.m || j >= g.n) return;
     const int64_t off = c_offset<GS>(g, i, j);
     const T ax = (T)g.alpha_re;
-    if (g.c_half) {
+    if (HC && g.c_half) {
         // beta is already binary16; the update in double, one rounding to binary16
         _Float16 *c = (_Float16 *)g.C;
         const double t = (double)(ax * acc);
@@ -541,12 +543,12 @@ __device__ __forceinline__ void cupdate(const GemmArgs &g, W *c2, const W *cin2,
     }
 }
 
-template <class T, bool GS = false>
+template <class T, bool GS = false, bool HC = false>
 __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_t j, T re, T im) {
     if (i >= g.m || j >= g.n) return;
     const int64_t off = 2 * c_offset<GS>(g, i, j);
     const T ar = (T)g.alpha_re, ai = (T)g.alpha_im;
-    if (g.c_half) {
+    if (HC && g.c_half) {
         // alpha*AB in the computation precision, the beta update in double,
         // one rounding to binary16 per part
         _Float16 *c = (_Float16 *)g.C + off;
@@ -740,11 +742,11 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
     // A split workgroup stores its partial (re, im) instead.
     auto put_cplx = [&](int64_t i, int64_t j, T re, T im) {
         if (nsplit > 1) store_partial(g, split, i, j, re, im);
-        else update_cplx<T, !FAST>(g, i, j, re, im);
+        else update_cplx<T, !FAST, true>(g, i, j, re, im);
     };
     auto put_real = [&](int64_t i, int64_t j, T re) {
         if (nsplit > 1) store_partial(g, split, i, j, re, (T)0);
-        else update_real<T, !FAST>(g, i, j, re);
+        else update_real<T, !FAST, true>(g, i, j, re);
     };
     const int ml = lane & 15;
 #pragma unroll

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
                 for (int q = 0; q < WMB / 2; ++q) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    update_cplx<float, !FAST>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
+                    update_cplx<float, !FAST, true>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
                 }
             } else if constexpr (NDBL) {
                 if ((b & 1) == 0) {
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
                     for (int a = 0; a < WMB; ++a) {
                         const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                         const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
-                        update_cplx<float, !FAST>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
+                        update_cplx<float, !FAST, true>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
                     }
                 }
             } else {
@@ -219,8 +219,8 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
                 for (int a = 0; a < WMB; ++a) {
                     const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                     const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    if constexpr (CCPLX) update_cplx<float, !FAST>(g, i, j, acc[a][b][v], 0.0f);
-                    else update_real<float, !FAST>(g, i, j, acc[a][b][v]);
+                    if constexpr (CCPLX) update_cplx<float, !FAST, true>(g, i, j, acc[a][b][v], 0.0f);
+                    else update_real<float, !FAST, true>(g, i, j, acc[a][b][v]);
                 }
             }
         }

@@ -3,8 +3,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 
+#include <map>
 #include <mutex>
+#include <utility>
 
 #include "md_half.h"
 #include "md_internal.h"
@@ -105,8 +108,8 @@ __global__ __launch_bounds__(256) void md_split_reduce(GemmArgs g) {
             re += p[s * stride];
             im += p[s * stride + 1];
         }
-        if (g.c_cplx) update_cplx<T, true>(g, i, j, re, im);
-        else update_real<T, true>(g, i, j, re);
+        if (g.c_cplx) update_cplx<T, true, true>(g, i, j, re, im);
+        else update_real<T, true, true>(g, i, j, re);
     }
 }
 
@@ -126,7 +129,11 @@ static int cu_count() {
 // fewer tiles than half the CUs, at least 4 k-tiles per split (2: measured
 // slower at 256), at most 16.
 static int split_count(int prec, int cs, const GemmArgs &a, int64_t tiles) {
-    if (prec != PREC_S && prec != PREC_D) return 1;
+    static const bool enabled = [] {
+        const char *e = getenv("MDGEMM_SPLITK");  // "0": never split
+        return !(e && e[0] == '0');
+    }();
+    if (!enabled || (prec != PREC_S && prec != PREC_D)) return 1;
     const int cus = cu_count();
     if (tiles * 2 > cus) return 1;
     int bm, bn, bk;
@@ -139,32 +146,27 @@ static int split_count(int prec, int cs, const GemmArgs &a, int64_t tiles) {
     return s > 1 ? (int)s : 1;
 }
 
-// The split workspaces come from a stream-ordered pool of the library's own
-// (one per device, created on first use) that keeps freed memory for reuse,
-// so an allocation after a synchronisation does not go back to the driver.
-static std::mutex g_pool_mu;
-static hipMemPool_t g_pools[64];
-static bool g_pool_tried[64];
-static hipMemPool_t split_pool() {
+// Split workspaces: one per (device, stream), grown on demand and kept for the
+// life of the process.  Work on one stream runs in order, so the calls that
+// share a workspace never overlap; different streams have their own.  Growth
+// frees the old buffer in stream order (after the work already enqueued).
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_ws;
+static void *split_workspace(hipStream_t s, size_t bytes) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (!g_pool_tried[dev]) {
-        g_pool_tried[dev] = true;
-        hipMemPoolProps props = {};
-        props.allocType = hipMemAllocationTypePinned;
-        props.location.type = hipMemLocationTypeDevice;
-        props.location.id = dev;
-        hipMemPool_t p = nullptr;
-        if (hipMemPoolCreate(&p, &props) == hipSuccess) {
-            uint64_t keep = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
-            g_pools[dev] = p;
-        } else {
-            (void)hipGetLastError();
-        }
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto &e = g_ws[std::make_pair(dev, s)];
+    if (e.first && e.second >= bytes) return e.first;
+    void *p = nullptr;
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
     }
-    return g_pools[dev];
+    if (e.first) (void)hipFreeAsync(e.first, s);
+    e.first = p;
+    e.second = bytes;
+    return p;
 }
 
 int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg) {
@@ -179,13 +181,9 @@ int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg)
     if (a.splits > 1) {
         const size_t esz = prec == PREC_D ? sizeof(double) : sizeof(float);
         const size_t bytes = (size_t)a.splits * (size_t)a.m * (size_t)a.n * 2 * esz;
-        // stream-ordered workspace; without it the product runs unsplit
-        hipMemPool_t pool = split_pool();
-        if (!pool || hipMallocFromPoolAsync(&a.part, bytes, pool, s) != hipSuccess) {
-            (void)hipGetLastError();
-            a.part = nullptr;
-            a.splits = 1;
-        }
+        // the stream's workspace; without it the product runs unsplit
+        a.part = split_workspace(s, bytes);
+        if (!a.part) a.splits = 1;
     }
     kParts[prec][cs](a, s, (unsigned)(n * a.splits));
     if (a.splits > 1) {
@@ -194,7 +192,6 @@ int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg)
         if (blocks > 4096) blocks = 4096;
         if (prec == PREC_D) hipLaunchKernelGGL(md_split_reduce<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL(md_split_reduce<float>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-        (void)hipFreeAsync(a.part, s);
     }
     return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
 }
