@@ -739,48 +739,63 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
 
     // Epilogue.  acc[a][b] item v is C'(row m = wm0 + 16a + (lane & 15),
     //                                   col n = wn0 + 16b + acc_row(lane, v)).
-    // A split workgroup stores its partial (re, im) instead.
-    auto put_cplx = [&](int64_t i, int64_t j, T re, T im) {
-        if (nsplit > 1) store_partial(g, split, i, j, re, im);
-        else update_cplx<T, !FAST, true>(g, i, j, re, im);
-    };
-    auto put_real = [&](int64_t i, int64_t j, T re) {
-        if (nsplit > 1) store_partial(g, split, i, j, re, (T)0);
-        else update_real<T, !FAST, true>(g, i, j, re);
-    };
-    const int ml = lane & 15;
+    // A split workgroup stores its partial (re, im) instead.  Split and
+    // binary16-C stores are decided once per workgroup, so the common case
+    // keeps the plain epilogue's code.
+    auto epilogue = [&](auto general_tag) {
+        constexpr bool GEN = decltype(general_tag)::value;
+        auto put_cplx = [&](int64_t i, int64_t j, T re, T im) {
+            if constexpr (GEN) {
+                if (nsplit > 1) store_partial(g, split, i, j, re, im);
+                else update_cplx<T, !FAST, true>(g, i, j, re, im);
+            } else {
+                update_cplx<T, !FAST, false>(g, i, j, re, im);
+            }
+        };
+        auto put_real = [&](int64_t i, int64_t j, T re) {
+            if constexpr (GEN) {
+                if (nsplit > 1) store_partial(g, split, i, j, re, (T)0);
+                else update_real<T, !FAST, true>(g, i, j, re);
+            } else {
+                update_real<T, !FAST, false>(g, i, j, re);
+            }
+        };
+        const int ml = lane & 15;
 #pragma unroll
-    for (int b = 0; b < WNB; ++b) {
+        for (int b = 0; b < WNB; ++b) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int nl = acc_row<T>(lane, v);
-            if constexpr (MDBL) {
+            for (int v = 0; v < 4; ++v) {
+                const int nl = acc_row<T>(lane, v);
+                if constexpr (MDBL) {
 #pragma unroll
-                for (int q = 0; q < WMB / 2; ++q) {
-                    const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
-                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    put_cplx(i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
-                }
-            } else if constexpr (NDBL) {
-                if ((b & 1) == 0) {
+                    for (int q = 0; q < WMB / 2; ++q) {
+                        const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
+                        const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                        put_cplx(i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
+                    }
+                } else if constexpr (NDBL) {
+                    if ((b & 1) == 0) {
+#pragma unroll
+                        for (int a = 0; a < WMB; ++a) {
+                            const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
+                            const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
+                            put_cplx(i, j, acc[a][b][v], acc[a][b + 1][v]);
+                        }
+                    }
+                } else {
 #pragma unroll
                     for (int a = 0; a < WMB; ++a) {
                         const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
-                        const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
-                        put_cplx(i, j, acc[a][b][v], acc[a][b + 1][v]);
+                        const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                        if constexpr (CCPLX) put_cplx(i, j, acc[a][b][v], (T)0);
+                        else put_real(i, j, acc[a][b][v]);
                     }
-                }
-            } else {
-#pragma unroll
-                for (int a = 0; a < WMB; ++a) {
-                    const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
-                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    if constexpr (CCPLX) put_cplx(i, j, acc[a][b][v], (T)0);
-                    else put_real(i, j, acc[a][b][v]);
                 }
             }
         }
-    }
+    };
+    if (nsplit > 1 || g.c_half) epilogue(std::true_type{});
+    else epilogue(std::false_type{});
 }
 
 }  // namespace md
