@@ -21,6 +21,9 @@ What fixes what (the paper is Van Zee, Parikh, van de Geijn, FLAME WN #89):
   * pin_scalars                     -- Section 6 scalar policies (golden
                                        fixture) and BLAS quick-return rules
   * pin_transpose                   -- Section 1's op(A) = A^T / A^H variants
+  * pin_bound_term                  -- the bound term sum_p |op(A)_ip||op(B)_pj|
+                                       of the tolerance: numpy on the moduli
+  * pin_gemm_at                     -- the sampled evaluator equals the full one
 """
 import itertools
 import os
@@ -544,9 +547,63 @@ def pin_half_products(o):
     return fails
 
 
+def pin_bound_term(o):
+    """The bound term g_ij = sum_p |op(A)_ip| |op(B)_pj| (complex modulus) that
+    the error bound |C_gpu - C_ref| <= 4 k u_x g + 4 u_C |C_ref| scales by: for
+    all 64 storage combinations and all 16 op pairs it must equal numpy's
+    product of the elementwise moduli of op(A) and op(B) (the promoted stored
+    values), to 1e-14 relative.  m != n, so a swapped index shows."""
+    fails = []
+    m, n, k = 5, 3, 7
+    for i, (tc, ta_, tb_) in enumerate(itertools.product(TAGS, TAGS, TAGS)):
+        for ta, tb in itertools.product("NTCR", "NTCR"):
+            A, B, C, ar, br = _operands(ta_, tb_, tc, m, n, k, ta, tb, seed=900 + i)
+            alpha = 1.5 + (0.25j if o.case(tc, ta_, tb_) in ("0", "3") else 0)
+            st, _, g = _call(o, ta, tb, m, n, k, alpha, A, ta_, B, tb_, -0.5, C, tc)
+            if st != 0:
+                fails.append("bound term %s%s%s %s%s status %d" % (tc, ta_, tb_, ta, tb, st))
+                continue
+            want = np.abs(_op(A, A.shape[0], A.shape[1], ta)) @ np.abs(_op(B, B.shape[0], B.shape[1], tb))
+            err = np.max(np.abs(g - want) / np.maximum(want, 1e-300))
+            if not err < 1e-14:
+                fails.append("bound term %s%s%s %s%s rel err %.3g" % (tc, ta_, tb_, ta, tb, err))
+                break
+    return fails
+
+
+def pin_gemm_at(o):
+    """The sampled evaluator (used where the full product is too large) is the
+    same definition: at random (row, col) pairs of a non-square result it
+    equals the full evaluator's value and bound term bit for bit.  Operands are
+    allocated for max(m, n) rows and columns so that an index mix-up reads
+    other stored values instead of leaving the buffers."""
+    fails = []
+    m, n, k = 9, 4, 6
+    big = max(m, n)
+    rng = np.random.Generator(np.random.PCG64(97))
+    for i, (tc, ta_, tb_, ta, tb) in enumerate((("z", "c", "d", "N", "N"), ("d", "z", "z", "T", "C"),
+                                                 ("c", "s", "z", "C", "R"), ("s", "d", "s", "N", "T"),
+                                                 ("z", "z", "z", "R", "N"), ("c", "z", "c", "T", "T"))):
+        A = inputs.matrix(big, big, ta_, 700 + i)
+        B = inputs.matrix(big, big, tb_, 710 + i)
+        C = inputs.matrix(big, big, tc, 720 + i)
+        alpha = 0.75 + (0.5j if o.case(tc, ta_, tb_) == "3" else 0)
+        st, full, gfull = o.gemm(ta, tb, m, n, k, alpha, A, ta_, big, B, tb_, big, -0.5, C, tc, big)
+        rows = rng.integers(0, m, 40)
+        cols = rng.integers(0, n, 40)
+        st2, vals, g = o.gemm_at(ta, tb, m, n, k, alpha, A, ta_, big, B, tb_, big, -0.5, C, tc, big, rows, cols)
+        if st != 0 or st2 != 0:
+            fails.append("gemm_at %s%s%s status %d/%d" % (tc, ta_, tb_, st, st2))
+            continue
+        if not (np.array_equal(vals, full[rows, cols]) and np.array_equal(g, gfull[rows, cols])):
+            fails.append("gemm_at %s%s%s %s%s differs from the full evaluation" % (tc, ta_, tb_, ta, tb))
+    return fails
+
+
 ALL_PINS = (pin_case_table, pin_flops, pin_same_type, pin_domain_identities,
             pin_exact_integers, pin_exact_rational, pin_1m_equations, pin_scalars,
-            pin_transpose, pin_strides, pin_literal_alpha, pin_half_decoding, pin_half_products)
+            pin_transpose, pin_strides, pin_literal_alpha, pin_half_decoding, pin_half_products,
+            pin_bound_term, pin_gemm_at)
 
 
 def run_all(o):

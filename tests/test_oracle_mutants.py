@@ -44,6 +44,14 @@ MUTANTS = {
     "half_subnormal_scale": ("v = ldexp((double)f, -24);", "v = ldexp((double)f, -25);"),
     "half_complex_parts_swapped": ("*im = half_value(((const uint16_t *)X)[2 * idx + 1]);",
                                    "*im = half_value(((const uint16_t *)X)[2 * idx]);"),
+    "bound_term_doubled": ("g += sqrt(ar * ar + ai * ai) * sqrt(br * br + bi * bi);",
+                           "g += 2.0 * sqrt(ar * ar + ai * ai) * sqrt(br * br + bi * bi);"),
+    "bound_term_l1": ("g += sqrt(ar * ar + ai * ai) * sqrt(br * br + bi * bi);",
+                      "g += (fabs(ar) + fabs(ai)) * (fabs(br) + fabs(bi));"),
+    "bound_term_real_parts": ("g += sqrt(ar * ar + ai * ai) * sqrt(br * br + bi * bi);",
+                              "g += fabs(ar) * fabs(br);"),
+    "gemm_at_rows_cols_swapped": ("beta_re, beta_im, C, dtc, 1, ldc, rows[t], cols[t],",
+                                  "beta_re, beta_im, C, dtc, 1, ldc, cols[t], rows[t],"),
     "flops_case2": ("double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 4.0 : 8.0);",
                     "double f = (ncomplex <= 1) ? 2.0 : (ncomplex == 2 ? 8.0 : 8.0);"),
 }
