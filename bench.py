@@ -6,20 +6,22 @@ combinations of (C, A, B) in {s, d, c, z}^3 times computation precision
 U[-1, 1] per real/imaginary part (seeded), alpha = 1.5, beta = -0.5, no
 transpose.  Inputs are resident in HBM before timing starts.
 
-Reported (one JSON line):
+Reported: one compact JSON line on stdout (the last line), with
   value        aggregate GFLOP/s of the sweep: sum of the paper's minimum flop
                counts (2/4/8 mnk per case) / time of the step
-  per_combo    per combination: p50 GFLOP/s, p50/p99 latency, and the ratio to
-               the same-GPU native kernel the paper uses as its reference
-               (sgemm/dgemm for cases 0-2, cgemm/zgemm for case 3, at the
-               computation precision; torch.matmul -> hipBLASLt/rocBLAS)
+  vs_native    ratio of each combination's p50 GFLOP/s to the same-GPU native
+               kernel the paper uses as its reference (sgemm/dgemm for cases
+               0-2, cgemm/zgemm for case 3, at the computation precision;
+               torch.matmul -> hipBLASLt/rocBLAS), timed once per step between
+               the sweep's steps: min, median, count >= 0.9, worst five
   roofline     dominant kernel's achieved TFLOP/s (algorithmic flops / its
                measured duration, HIP events on its stream) vs the MFMA peak
-  per_combo.speedup_vs_adhoc
-               time of the ad-hoc alternative (cast and copy every operand to
+  vs_adhoc     time of the ad-hoc alternative (cast and copy every operand to
                the domain's computation type with torch, vendor GEMM, update,
-               cast back) over mdgemm's
-  cpu_baseline the FP64 oracle timed on this host on a bounded sample
+               cast back) over mdgemm's: median and minimum
+  cpu_baseline the FP64 oracle timed on this host's cores on a bounded sample
+and, before it, the per-combination and per-kernel record (p50/p99 latency,
+GFLOP/s, ratios) as one '# detail' line on stderr or in the --detail file.
 
     python bench.py [--steps K] [--warmup W] [--size N] [--combos zcd,sss] [--no-cpu] [--no-adhoc]
 """
@@ -52,6 +54,9 @@ def parse():
     p.add_argument("--no-native", action="store_true")
     p.add_argument("--no-adhoc", action="store_true", help="skip the ad-hoc (cast, copy, vendor GEMM) baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--detail", type=str, default="",
+                   help="sweep: write the per-combination and per-kernel record to this file "
+                        "(default: one '# detail' line on stderr)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain copy kernel of known size (HBM counter calibration)")
     p.add_argument("--check", action="store_true", help="grouped: check every product against the oracle")
@@ -98,12 +103,15 @@ def make_operands(n, seed=1901):
     return ops
 
 
-def native_times(n, reps=20):
-    """p50 seconds of torch.matmul per dtype (the native same-type GEMM)."""
+NATIVE = (("sgemm", "float32", 2), ("dgemm", "float64", 2), ("cgemm", "complex64", 8), ("zgemm", "complex128", 8))
+
+
+def native_operands(n):
+    """Operands of the native same-type GEMMs (torch.matmul), one set per dtype."""
     import torch
     res = {}
-    for name, dt, fl in (("sgemm", torch.float32, 2), ("dgemm", torch.float64, 2),
-                         ("cgemm", torch.complex64, 8), ("zgemm", torch.complex128, 8)):
+    for name, dtn, fl in NATIVE:
+        dt = getattr(torch, dtn)
         g = torch.Generator(device="cuda").manual_seed(5)
         if dt.is_complex:
             rdt = torch.float32 if dt == torch.complex64 else torch.float64
@@ -115,21 +123,42 @@ def native_times(n, reps=20):
             a = torch.rand(n, n, device="cuda", dtype=dt, generator=g) * 2 - 1
             b = torch.rand(n, n, device="cuda", dtype=dt, generator=g) * 2 - 1
         c = torch.empty(n, n, device="cuda", dtype=dt)
-        for _ in range(3):
+        for _ in range(2):
             torch.matmul(a, b, out=c)
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            torch.matmul(a, b, out=c)
-            e1.record()
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1) / 1e3)
-        res[name] = {"p50_s": float(np.median(ts)), "gflops": fl * n ** 3 / float(np.median(ts)) / 1e9}
-        del a, b, c
-        torch.cuda.empty_cache()
+        res[name] = (a, b, c, fl)
+    torch.cuda.synchronize()
+    return res
+
+
+def native_once(nops, stream):
+    """One timed call of each native GEMM on `stream` (HIP events); seconds."""
+    import torch
+    evs = []
+    for name, (a, b, c, fl) in nops.items():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        torch.matmul(a, b, out=c)
+        e1.record(stream)
+        evs.append((name, e0, e1))
+    torch.cuda.synchronize()
+    return {name: e0.elapsed_time(e1) / 1e3 for name, e0, e1 in evs}
+
+
+def native_times(n, reps=20):
+    """p50 seconds of torch.matmul per dtype (the native same-type GEMM)."""
+    import torch
+    nops = native_operands(n)
+    ts = {name: [] for name in nops}
+    for _ in range(reps):
+        for name, t in native_once(nops, torch.cuda.current_stream()).items():
+            ts[name].append(t)
+    res = {}
+    for name, (a, b, c, fl) in nops.items():
+        p50 = float(np.median(ts[name]))
+        res[name] = {"p50_s": p50, "gflops": fl * n ** 3 / p50 / 1e9}
+    del nops
+    torch.cuda.empty_cache()
     return res
 
 
@@ -240,37 +269,80 @@ def copy_calibration(nbytes=256 << 20, reps=3):
     torch.cuda.synchronize()
 
 
-def cpu_baseline(budget_s):
-    """The oracle, as it is, timed single-threaded on this host: full columns
-    of C for dddd, zcdd and zzzd at 4096 (the sample), GFLOP/s counted with
-    the same algorithmic flops as the GPU."""
+# The paper's CPU figures are theoretical peaks per core (Section 8.1); it
+# prints no measured GFLOP/s.
+PAPER_CPU_PEAKS = {"ThunderX2 CN9975 2.2GHz": {"dp": 17.6, "sp": 35.2},
+                   "Xeon Platinum 8167M 2.0GHz": {"dp": 64.0, "sp": 128.0}}
+
+
+def host_cpu():
+    """(model name, logical CPUs this process may run on)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(budget_s, threads=0):
+    """The oracle, as it is, timed on this host's cores: whole columns of C
+    for dddd, zcdd and zzzd at 4096 (the sample), the columns of each
+    combination dealt to `threads` host threads (ctypes releases the GIL) for
+    about a third of the time budget; GFLOP/s counted with the same
+    algorithmic flops as the GPU."""
+    import concurrent.futures
+    import threading
     import oracle
     from paper_1901_06015_amd import inputs
     o = oracle.get()
+    model, nproc = host_cpu()
+    if threads <= 0:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or nproc
+    threads = max(1, min(threads, nproc))
     n = 4096
     total_fl, total_t, cols_done = 0.0, 0.0, {}
     per = budget_s / 3.0
+    rows = np.arange(n, dtype=np.int64)
     for cab in ("ddd", "zcd", "zzz"):
         tc, ta, tb = cab
         A = inputs.matrix(n, n, ta, 11)
         B = inputs.matrix(n, n, tb, 12)
         C = inputs.matrix(n, n, tc, 13)
         fac = CASE_FACTOR[o.case(tc, ta, tb)]
+        lock = threading.Lock()
+        nxt = [0]
         t0 = time.perf_counter()
-        j = 0
-        while time.perf_counter() - t0 < per:
-            rows = np.arange(n, dtype=np.int64)
-            cols = np.full(n, j, dtype=np.int64)
-            st, _, _ = o.gemm_at("N", "N", n, n, n, 1.5, A, ta, n, B, tb, n, -0.5, C, tc, n, rows, cols)
-            assert st == 0
-            j += 1
+
+        def worker():
+            done = 0
+            while time.perf_counter() - t0 < per:
+                with lock:
+                    j = nxt[0]
+                    nxt[0] += 1
+                if j >= n:
+                    break
+                cols = np.full(n, j, dtype=np.int64)
+                st, _, _ = o.gemm_at("N", "N", n, n, n, 1.5, A, ta, n, B, tb, n, -0.5, C, tc, n, rows, cols)
+                assert st == 0
+                done += 1
+            return done
+
+        with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+            done = sum(ex.map(lambda _: worker(), range(threads)))
         dt = time.perf_counter() - t0
-        total_fl += fac * n * n * j
+        total_fl += fac * n * n * done
         total_t += dt
-        cols_done[cab + "d"] = j
-    return {"value": total_fl / total_t / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "full columns of C at m=n=k=4096 for %s (single thread, FP64 triple loop, %.1f s)"
-                      % (", ".join("%s:%d cols" % kv for kv in cols_done.items()), total_t)}
+        cols_done[cab + "d"] = done
+    value = total_fl / total_t / 1e9
+    return {"value": round(value, 2), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "per_core": round(value / threads, 3), "cpu": model, "nproc": nproc,
+            "sample": "whole columns of C at m=n=k=4096 (%s), FP64 triple loop, %d threads, %.1f s"
+                      % (", ".join("%s:%d" % kv for kv in cols_done.items()), threads, total_t),
+            "paper_peak_per_core": PAPER_CPU_PEAKS}
 
 
 def precision_workload(args):
@@ -900,6 +972,10 @@ def main():
         torch.cuda.synchronize()
         print("# warmup %d done" % w, file=sys.stderr, flush=True)
 
+    # the native same-type GEMMs are timed once per step, after the sweep's
+    # closing event, so that they see the same clocks and thermal state
+    nops = native_operands(n) if not args.no_native else {}
+    nat_ts = {name: [] for name in nops}
     times = {c: [] for c in todo}
     step_ms = []
     for s in range(args.steps):
@@ -918,6 +994,9 @@ def main():
         for cabx, a, b in evs:
             times[cabx].append(a.elapsed_time(b) / 1e3)
         step_ms.append(e_start.elapsed_time(prev))
+        if nops:
+            for name, t in native_once(nops, stream).items():
+                nat_ts[name].append(t)
         print("# step %d: %.1f ms" % (s, step_ms[-1]), file=sys.stderr, flush=True)
 
     flops = {c: plans[c]["flops"] for c in todo}
@@ -925,12 +1004,18 @@ def main():
     ms = float(np.median(step_ms))
     value = step_flops / (ms / 1e3) / 1e9
 
-    native = native_times(n) if not args.no_native else {}
+    native = {}
+    for name, (a, b, c, fl) in nops.items():
+        p50 = float(np.median(nat_ts[name]))
+        native[name] = {"p50_s": p50, "gflops": fl * n ** 3 / p50 / 1e9}
+    del nops
+    torch.cuda.empty_cache()
     adhoc = adhoc_times(ops, todo) if not args.no_adhoc else {}
     if args.calibrate_copy:
         copy_calibration()
     per = {}
     by_kernel = {}
+    short = {}
     for c in todo:
         ts = np.array(times[c])
         p50 = float(np.median(ts))
@@ -938,11 +1023,13 @@ def main():
         nat = native.get(native_for(plans[c]["case"], c[3]))
         per[c] = {"case": plans[c]["case"], "gflops": round(gf, 1),
                   "vs_native": round(gf / nat["gflops"], 3) if nat else None,
-                  "p50_ms": round(p50 * 1e3, 4), "p99_ms": round(float(np.percentile(ts, 99)) * 1e3, 4)}
+                  "p50_ms": round(p50 * 1e3, 4), "p99_ms": round(float(np.percentile(ts, 99)) * 1e3, 4),
+                  "kernel": plans[c]["kernel"]}
         if c in adhoc:
             per[c]["adhoc_ms"] = round(adhoc[c] * 1e3, 4)
             per[c]["speedup_vs_adhoc"] = round(adhoc[c] / p50, 3)
         k = kernel_symbol(plans[c])
+        short[k] = plans[c]["kernel"]
         bk = by_kernel.setdefault(k, {"flops": 0.0, "time": 0.0, "launches": 0, "bytes": 0.0})
         bk["flops"] += flops[c] * len(ts)
         bk["bytes"] += algorithmic_bytes(c, n) * len(ts)
@@ -952,7 +1039,22 @@ def main():
     dk = by_kernel[dom]
     prec = "f64" if "<double" in dom else "f32"
     achieved = dk["flops"] / dk["time"] / 1e12
-    ratios = [v["vs_native"] for v in per.values() if v["vs_native"] is not None]
+    ratios = {c: v["vs_native"] for c, v in per.items() if v["vs_native"] is not None}
+    rv = list(ratios.values())
+    worst = sorted(ratios, key=lambda c: ratios[c])[:5]
+    traffic = traffic_record(dom)
+    # everything per combination and per kernel goes to the detail record
+    detail = {"per_combo": per,
+              "per_kernel": {k: {"short": short[k], "tflops": round(v["flops"] / v["time"] / 1e12, 2),
+                                 "avg_ms": round(v["time"] / v["launches"] * 1e3, 4),
+                                 "launches": v["launches"]} for k, v in sorted(by_kernel.items())},
+              "native_p50_ms": {k: round(v["p50_s"] * 1e3, 4) for k, v in native.items()},
+              "dominant_kernel_symbol": dom, "traffic": traffic}
+    if args.detail:
+        with open(args.detail, "w") as f:
+            json.dump(detail, f, indent=1)
+    else:
+        print("# detail " + json.dumps(detail), file=sys.stderr, flush=True)
     out = {
         "metric": "GFLOP/s per type combo at m=n=k=4096 vs native same-type; p50/p99 latency",
         "value": round(value, 1),
@@ -972,33 +1074,30 @@ def main():
                    "m": n, "n": n, "k": n, "combos": len(todo)},
         "latency_ms": {"p50_of_p50": round(float(np.median([v["p50_ms"] for v in per.values()])), 4),
                        "max_p99": round(max(v["p99_ms"] for v in per.values()), 4)},
-        "vs_native": {"min": min(ratios) if ratios else None,
-                      "median": float(np.median(ratios)) if ratios else None,
-                      "combos_at_or_above_0.9": sum(1 for r in ratios if r >= 0.9)},
-        "native_gflops": {k: round(v["gflops"], 1) for k, v in native.items()},
-        "vs_adhoc": ({"median_speedup": float(np.median([v["speedup_vs_adhoc"] for v in per.values()])),
-                      "min_speedup": min(v["speedup_vs_adhoc"] for v in per.values()),
-                      "method": "cast+copy to the domain's computation type, torch.matmul, update, cast back"}
+        "vs_native": ({"min": min(rv), "median": round(float(np.median(rv)), 3),
+                       "ge_0.9": sum(1 for r in rv if r >= 0.9), "of": len(rv),
+                       "worst": {c: ratios[c] for c in worst},
+                       "native_gflops": {k: round(v["gflops"], 1) for k, v in native.items()},
+                       "timing": "vendor GEMMs timed once per step, interleaved with the sweep; medians"}
+                      if rv else None),
+        "vs_adhoc": ({"median": round(float(np.median([v["speedup_vs_adhoc"] for v in per.values()])), 3),
+                      "min": min(v["speedup_vs_adhoc"] for v in per.values())}
                      if adhoc else None),
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+        "roofline": {"bound": "mfma", "kernel": short[dom], "achieved": round(achieved, 2),
                      "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_TFLOPS[prec], 4),
-                     "traffic": traffic_record(dom),
-                     "algorithmic_bytes_per_launch": round(dk["bytes"] / dk["launches"]),
-                     "kernel_src": kernel_source_sha(),
-                     "launches": dk["launches"],
-                     "avg_launch_ms": round(dk["time"] / dk["launches"] * 1e3, 4)},
-        "per_kernel": {k: {"tflops": round(v["flops"] / v["time"] / 1e12, 2),
-                           "avg_ms": round(v["time"] / v["launches"] * 1e3, 4),
-                           "launches": v["launches"]} for k, v in sorted(by_kernel.items())},
-        "per_combo": per,
+                     "traffic": round(traffic["bytes"]) if traffic else None,
+                     "algorithmic_bytes": round(dk["bytes"] / dk["launches"]),
+                     "algorithmic_flops": round(dk["flops"] / dk["launches"]),
+                     "avg_launch_ms": round(dk["time"] / dk["launches"] * 1e3, 4),
+                     "launches": dk["launches"], "kernel_src": kernel_source_sha()},
     }
     if not args.no_cpu:
         print("# cpu baseline (%.0f s)" % args.cpu_seconds, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

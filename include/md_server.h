@@ -4,7 +4,7 @@
  *
  * This serving layer is an addition of this library; the product each request
  * computes is mdgemm's (Van Zee, Parikh, van de Geijn, Section 1 operation,
- * Figure "mixeddom" cases, Section 6 scalars), written out of place: the
+ * Figure "mixeddom" cases, Section 7 scalars), written out of place: the
  * output C := beta*C_in + alpha*op(A)*op(B) goes to fresh device memory and
  * the input C_in is only read, so one resident C_in can serve many requests.
  *

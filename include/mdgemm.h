@@ -9,10 +9,10 @@
  * precisions.  The operation and the three op() variants are those of the
  * BLAS gemm (Van Zee, Parikh, van de Geijn, "Supporting mixed-datatype matrix
  * multiplication within the BLIS framework", Section 1), plus conjugation
- * without transposition ('R', Section 2); the domain of the computation
- * follows from which operands are complex (Section 3.2, Figure "mixeddom");
+ * without transposition ('R', Section 3); the domain of the computation
+ * follows from which operands are complex (Section 4.2, Figure "mixeddom");
  * the computation precision and the target types of A and B follow Section
- * 4.1; the scalar policies follow Section 6.
+ * 5.1; the scalar policies follow Section 7.
  *
  * Storage conventions (all entry points but mdgemm_strided, which takes row
  * and column strides):
@@ -27,9 +27,15 @@
  *     the call returns before it completes: the caller keeps every buffer alive
  *     until the stream has finished;
  *   - on any error return nothing is enqueued and C is unmodified;
- *   - a product with few output tiles and a deep k may take a workspace for
- *     its split-k partial products from the library's own stream-ordered
- *     memory pool (released to the pool on the same stream).
+ *   - device memory: a product with few output tiles (fewer than half the
+ *     CUs) and a deep k splits k over workgroups and keeps their partial
+ *     products in a workspace of the library, one per (device, stream):
+ *     allocated with hipMallocAsync on that stream when first needed, grown
+ *     on demand (the old buffer freed in stream order) and kept until the
+ *     process ends, at most about 100 MB per stream.  Calls on one stream may
+ *     come from several host threads.  With MDGEMM_SPLITK=0 in the
+ *     environment products are never split and mdgemm allocates no device
+ *     memory.
  *
  * Return codes: 0 on success; -i when argument i (1-based, in mdgemm's order)
  * is invalid; positive MD_ERR_* codes otherwise (see mdgemm_strerror).
@@ -46,7 +52,7 @@ extern "C" {
 /* Storage type of one operand (domain x precision, Section 1's s/d/c/z). */
 typedef enum {
     MD_S = 0, MD_D = 1, MD_C = 2, MD_Z = 3,
-    /* Half precision, the next storage precision Section 4's summary names
+    /* Half precision, the next storage precision Section 5's summary names
      * (an addition of this library): IEEE 754 binary16 (MD_H) and complex
      * binary16 with interleaved re, im (MD_HC).  A half C is written by every
      * kernel; binary16 A and B together run on the fast loads under the
@@ -55,7 +61,7 @@ typedef enum {
     MD_H = 4, MD_HC = 5
 } md_dt;
 
-/* Computation precision (Section 4.1.1).  MD_COMP_DEFAULT selects the storage
+/* Computation precision (Section 5.1.1).  MD_COMP_DEFAULT selects the storage
  * precision of C.  MD_COMP_S_BF16X3 has single-precision semantics but forms
  * each real product from bfloat16 halves (hi*hi + hi*lo + lo*hi) on the
  * bf16 matrix cores with FP32 accumulation; it is an addition of this
@@ -73,17 +79,17 @@ typedef enum {
     MD_COMP_H = 3,
     /* Flag, OR'ed into MD_COMP_S, MD_COMP_D or MD_COMP_S_BF16X3 (not into
      * MD_COMP_DEFAULT): a complex alpha is applied as given in the six mixed
-     * cases too, under the literal interpretation Section 6.2 describes (all
+     * cases too, under the literal interpretation Section 7.2 describes (all
      * five operands in their own domains), instead of being refused.  With C
      * real (cases 1a, 1b, 2ab) alpha is folded into the complex operand as it
      * is staged (Re(alpha*A), Re(alpha*B), alpha*A: the packing the paper
-     * suggests in a footnote to Section 6.2), so the flop count stays the
+     * suggests in a footnote to Section 7.2), so the flop count stays the
      * case's minimum; with C complex (1c, 2ac, 2bc) the epilogue multiplies
      * by the complex alpha.  An extension of the paper's policy. */
     MD_COMP_LITERAL_ALPHA = 0x100
 } md_comp;
 
-/* alpha and beta are always passed as complex double; see Section 6 for how
+/* alpha and beta are always passed as complex double; see Section 7 for how
  * each case uses them. */
 typedef struct { double re, im; } md_scalar;
 
@@ -101,7 +107,7 @@ typedef enum {
 
 /* Status codes. */
 #define MD_OK 0
-#define MD_ERR_ALPHA_IMAG 1  /* Im(alpha) != 0 in case 1a, 1b, 1c, 2ab, 2ac or 2bc (Section 6.2) */
+#define MD_ERR_ALPHA_IMAG 1  /* Im(alpha) != 0 in case 1a, 1b, 1c, 2ab, 2ac or 2bc (Section 7.2) */
 #define MD_ERR_HIP 2         /* HIP launch or runtime failure */
 #define MD_ERR_BUDGET 3      /* a serving request exceeds the memory budget */
 #define MD_ERR_STATE 4       /* call not valid in the object's current state */
@@ -113,16 +119,16 @@ typedef enum {
  * Arguments (position in parentheses is the one reported as -i on error):
  *  (1) transa, (2) transb : 'N', 'T', 'C' (the BLAS) or 'R' (conjugate
  *        without transposing, the fourth value of the paper's hypothetical
- *        API, Section 2); lower case accepted.  On a real operand 'C' equals
+ *        API, Section 3); lower case accepted.  On a real operand 'C' equals
  *        'T' and 'R' equals 'N'.
  *  (3) m, (4) n, (5) k     : op(A) is m x k, op(B) is k x n, C is m x n; >= 0.
- *  (6) alpha               : cast to the computation precision (Section 6.1,
+ *  (6) alpha               : cast to the computation precision (Section 7.1,
  *        option 1).  Im(alpha) is ignored in case 0 and used in case 3; in the
  *        other six cases a non-zero Im(alpha) returns MD_ERR_ALPHA_IMAG unless
  *        comp carries MD_COMP_LITERAL_ALPHA.
  *  (7) A, (8) dta, (9) lda : operand A, its storage type, leading dimension.
  *  (10) B, (11) dtb, (12) ldb : operand B likewise.
- *  (13) beta               : cast to C's storage precision (Section 6.1,
+ *  (13) beta               : cast to C's storage precision (Section 7.1,
  *        option 1); Im(beta) is ignored when C is real.  beta == 0 means C is
  *        not read (NaN in C does not propagate).
  *  (14) C, (15) dtc, (16) ldc : operand C likewise; updated in place.
@@ -146,7 +152,7 @@ int mdgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
  * mdgemm_strided -- the same product with every operand addressed by its row
  * and column strides (element (i, j) of a stored operand at i*rs + j*cs
  * elements of its type), the storage description of the paper's hypothetical
- * API (Section 2; Section 3.3 for BLIS's row and column strides).  Strides are
+ * API (Section 3; Section 2.2.1 for BLIS's row and column strides).  Strides are
  * >= 1 and an operand's elements must not overlap: its columns lie apart
  * (cs >= rs*rows; column-major storage is rs == 1) or its rows do
  * (rs >= cs*cols; row-major storage is cs == 1); a stride along an extent of

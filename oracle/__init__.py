@@ -2,7 +2,7 @@
 
 A plain FP64 CPU evaluation of C := beta*C + alpha*op(A)*op(B) for operands
 independently stored as s/d/c/z (Van Zee, Parikh, van de Geijn: Section 1 for
-the operation, Figure "mixeddom" for the domain cases, Section 6 for scalars).
+the operation, Figure "mixeddom" for the domain cases, Section 7 for scalars).
 The arithmetic lives in ``md_oracle.c``; this module only marshals numpy
 buffers into it.  Only the tests, the smoke check and the benchmark's CPU
 baseline may import it; the GPU library never does.
@@ -91,7 +91,7 @@ class Oracle:
              beta, C, dtc, ldc, want_bound=True, literal_alpha=False):
         """Full reference.  Returns (status, cref complex128 (m, n), g float64 (m, n)).
         literal_alpha: apply a complex alpha as given in every case (the literal
-        interpretation of Section 6.2) instead of refusing it in the mixed cases."""
+        interpretation of Section 7.2) instead of refusing it in the mixed cases."""
         cref = np.zeros((max(m, 0), max(n, 0)), dtype=np.complex128, order="F")
         g = np.zeros((max(m, 0), max(n, 0)), dtype=np.float64, order="F") if want_bound else None
         fn = self.lib.md_oracle_gemm_literal if literal_alpha else self.lib.md_oracle_gemm

@@ -9,18 +9,18 @@
  *      operand has imaginary part 0; float -> double is exact);
  *   2. op(X) is X, X^T, X^H (Section 1, the nine BLAS variants) or conj(X),
  *      the conjugation without transposition of the paper's hypothetical
- *      API (Section 2); an element (r, c) of a stored operand lies at
+ *      API (Section 3); an element (r, c) of a stored operand lies at
  *      r * rstride + c * cstride elements from its origin, the row and
  *      column strides of that API (column-major: rstride 1, cstride = ld);
  *   3. for every (i, j) the sum over p runs in ascending order with the
  *      complex product written out in real arithmetic;
- *   4. the scalars follow Section 6: alpha is used as given (a complex alpha
+ *   4. the scalars follow Section 7: alpha is used as given (a complex alpha
  *      with a non-zero imaginary part is refused in the six mixed cases of
- *      Section 6.2, except by md_oracle_gemm_literal, which computes those
- *      cases under the literal interpretation Section 6.2 describes, all
+ *      Section 7.2, except by md_oracle_gemm_literal, which computes those
+ *      cases under the literal interpretation Section 7.2 describes, all
  *      five operands taken in their own domains; in case 0 the product is
  *      real so Re(alpha*AB) equals Re(alpha)*AB, the projection the paper
- *      describes); beta is reduced to Re(beta) when C is real (Section 6.2);
+ *      describes); beta is reduced to Re(beta) when C is real (Section 7.2);
  *   5. a real C keeps Re of the result.  Figure "mixeddom"'s interpretations
  *      (A Re(B), Re(A) B, Re(AB), AB into Re(C), complex products with an
  *      implicit zero imaginary part) are all what steps 1-5 give.
@@ -46,7 +46,7 @@ static int tag_complex(int dt) { return dt == T_C || dt == T_Z || dt == T_HC; }
 
 /* The value of a binary16 bit pattern (1 sign, 5 exponent bits biased by 15,
  * 10 fraction bits; exponent 0 = subnormal, 31 = infinity or NaN), exactly in
- * double: the additional precision the paper's Section 4 discussion leaves
+ * double: the additional precision the paper's Section 5 discussion leaves
  * room for. */
 static double half_value(uint16_t h)
 {
@@ -142,7 +142,7 @@ static int check_args(char ta, char tb, int64_t m, int64_t n, int64_t k,
     return ORACLE_OK;
 }
 
-/* Section 6.2: a non-zero Im(alpha) is refused in cases 1a,1b,1c,2ab,2ac,2bc. */
+/* Section 7.2: a non-zero Im(alpha) is refused in cases 1a,1b,1c,2ab,2ac,2bc. */
 static int alpha_refused(int dtc, int dta, int dtb, double alpha_im)
 {
     int cs = md_oracle_case(dtc, dta, dtb);
@@ -159,7 +159,7 @@ static void entry(char ta, char tb, int64_t k,
                   int64_t i, int64_t j, double *out_re, double *out_im, double *out_g)
 {
     double sr = 0.0, si = 0.0, g = 0.0;
-    /* Section 6.2: in case 0 a complex alpha is projected onto the real domain */
+    /* Section 7.2: in case 0 a complex alpha is projected onto the real domain */
     if (md_oracle_case(dtc, dta, dtb) == 0)
         alpha_im = 0.0;
     int use_ab = (k > 0) && (alpha_re != 0.0 || alpha_im != 0.0);

@@ -5,8 +5,8 @@
  *     C := beta*C + alpha*op(A)*op(B)
  * as stated in Van Zee, Parikh, van de Geijn, "Supporting mixed-datatype matrix
  * multiplication within the BLIS framework" (Section 1 for the operation and the
- * op() variants; Section 3.2 / Figure "mixeddom" for the eight domain cases;
- * Section 4 for precision; Section 6 for the scalar policies).
+ * op() variants; Section 4.2 / Figure "mixeddom" for the eight domain cases;
+ * Section 5 for precision; Section 7 for the scalar policies).
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
  * call this.  It shares no code, header, table or helper with the GPU library.
@@ -14,7 +14,7 @@
  * Storage tags: 0 = s (float), 1 = d (double), 2 = c (float complex,
  * interleaved re,im), 3 = z (double complex, interleaved), 4 = h (IEEE
  * binary16), 5 = hc (binary16 complex, interleaved): the half precision the
- * paper's Section 4 summary names as the next storage precision.  Matrices are
+ * paper's Section 5 summary names as the next storage precision.  Matrices are
  * column-major unless strides are given (md_oracle_gemm_gs); a leading
  * dimension or stride counts elements of the operand's own type.  Trans
  * letters: N, T, C (the BLAS) and R (conjugate without transposing).
@@ -27,7 +27,7 @@ extern "C" {
 #endif
 
 #define ORACLE_OK 0
-#define ORACLE_ERR_ALPHA_IMAG 1   /* Section 6.2: Im(alpha) != 0 in cases 1a,1b,1c,2ab,2ac,2bc */
+#define ORACLE_ERR_ALPHA_IMAG 1   /* Section 7.2: Im(alpha) != 0 in cases 1a,1b,1c,2ab,2ac,2bc */
 #define ORACLE_ERR_ARG (-1)       /* malformed arguments (trans letter, dims, tags, ld) */
 
 /* Domain case of Figure "mixeddom", encoded 0..7 as
@@ -55,7 +55,7 @@ int md_oracle_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                    const void *C, int dtc, int64_t ldc,
                    double *cref, double *g);
 
-/* The same under the literal interpretation of Section 6.2: a complex alpha
+/* The same under the literal interpretation of Section 7.2: a complex alpha
  * is applied as given in every case, so the six mixed cases accept
  * Im(alpha) != 0 (never returns ORACLE_ERR_ALPHA_IMAG). */
 int md_oracle_gemm_literal(char transa, char transb, int64_t m, int64_t n, int64_t k,
@@ -79,7 +79,7 @@ int md_oracle_gemm_at(char transa, char transb, int64_t m, int64_t n, int64_t k,
 
 /* The same definition with every operand addressed by its row and column
  * strides (element (r, c) at r*rs + c*cs elements; the hypothetical API of
- * Section 2: column-major, row-major or general storage), and trans letters
+ * Section 3: column-major, row-major or general storage), and trans letters
  * N, T, C or R (conjugate without transposing).  cref and g are column-major
  * m x n as in md_oracle_gemm.  Strides must be positive. */
 int md_oracle_gemm_gs(char transa, char transb, int64_t m, int64_t n, int64_t k,

@@ -2,7 +2,7 @@
 
 ``gemm`` takes 2-D torch tensors stored by columns (``stride(0) == 1``) or by
 rows (``stride(1) == 1``, torch's default) and passes their row and column
-strides to ``mdgemm_strided`` (the strided interface sketched in Section 2 of
+strides to ``mdgemm_strided`` (the strided interface sketched in Section 3 of
 the paper).  ``plan`` and grouped calls take column-major tensors, the BLAS
 layout of Section 1 (leading dimension ``stride(1)``); ``colmajor`` makes one.
 The storage type follows the tensor dtype: float32 -> s, float64 -> d,
@@ -88,7 +88,7 @@ def gemm(A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", comp=None, stream
     torch's current stream for C's device).  Each tensor may be stored by rows
     or by columns.  `comp` is None (C's precision), "s", "d" or "bf16x3".
     literal_alpha: apply a complex alpha as given in the mixed-domain cases
-    (the literal interpretation of Section 6.2) instead of refusing it.
+    (the literal interpretation of Section 7.2) instead of refusing it.
     Returns C."""
     if literal_alpha and not (isinstance(comp, str) and comp.endswith("+literal")):
         if comp is None:

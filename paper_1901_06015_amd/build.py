@@ -1,6 +1,6 @@
 """Build libmdgemm.so for gfx950 with hipcc (in-tree, no JIT cache).
 
-    python -m paper_1901_06015_amd.build
+    python -m paper_1901_06015_amd.build [--incremental]
 
 Every HIP source is compiled with packed-FP32 instructions disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``); the host planner is
@@ -26,7 +26,7 @@ HIP_FLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "--offload-arch=" + ARCH, "-I" + os.path.join(ROOT, "include")]
 
 # (source, extra defines, object name)
-SOURCES = [("mdgemm_kernels.hip", ["-DMD_KT=%d" % t, "-DMD_KCASE=%d" % c], "k_%d_%d.o" % (t, c))
+SOURCES = [("mdgemm_grouped_kernel.hip", [], "grouped_kernel.o")] + [("mdgemm_kernels.hip", ["-DMD_KT=%d" % t, "-DMD_KCASE=%d" % c], "k_%d_%d.o" % (t, c))
            for t in (1, 0, 2, 3) for c in (7, 4, 5, 6, 0, 1, 2, 3)] + [
     ("mdgemm_launch.hip", [], "launch.o"),
     ("mdgemm_grouped.hip", [], "grouped.o"),
@@ -35,11 +35,25 @@ SOURCES = [("mdgemm_kernels.hip", ["-DMD_KT=%d" % t, "-DMD_KCASE=%d" % c], "k_%d
 ]
 
 
-def _compile(entry, extra=(), build_dir=BUILD):
+def _newest_input(src):
+    """Modification time of the newest file an object of `src` depends on
+    (the source, every header under csrc/ and include/)."""
+    paths = [os.path.join(CSRC, src)]
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        paths += [os.path.join(d, f) for f in os.listdir(d) if f.endswith(".h")]
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def _compile(entry, extra=(), build_dir=BUILD, incremental=False):
     src, defs, objname = entry
     defs = list(defs) + list(extra)
     path = os.path.join(CSRC, src)
     obj = os.path.join(build_dir, objname)
+    stamp = obj + ".flags"
+    key = " ".join(defs)
+    if (incremental and os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key
+            and os.path.getmtime(obj) > _newest_input(src)):
+        return obj
     if src.endswith(".hip"):
         cmd = [HIPCC] + HIP_FLAGS + defs + ["-c", path, "-o", obj]
     else:
@@ -47,21 +61,32 @@ def _compile(entry, extra=(), build_dir=BUILD):
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), res.stderr))
+    with open(stamp, "w") as f:
+        f.write(key)
     return obj
 
 
-def build(verbose=True, defines=(), out=OUT, build_dir=BUILD):
+def build(verbose=True, defines=(), out=OUT, build_dir=BUILD, incremental=False):
     """Compile and link.  `defines` (e.g. ["-DMD_OCC=1"]) set the tuning knobs
-    of md_tile.h; `out` and `build_dir` place a variant build elsewhere."""
+    of md_tile.h; `out` and `build_dir` place a variant build elsewhere.
+    `incremental` keeps objects newer than their source and every header
+    (compiled with the same defines); the default recompiles everything."""
     os.makedirs(build_dir, exist_ok=True)
     srcs = [e for e in SOURCES if os.path.exists(os.path.join(CSRC, e[0]))]
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(int(os.environ.get('MAX_JOBS', '8')), len(srcs))) as ex:
-        objs = list(ex.map(lambda e: _compile(e, defines, build_dir), srcs))
+        objs = list(ex.map(lambda e: _compile(e, defines, build_dir, incremental), srcs))
     tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), res.stderr))
+    # a shared library links with undefined symbols; refuse one that would
+    # fail only when the GPU path first calls into the missing piece
+    und = subprocess.run(["nm", "-C", "-u", tmp], capture_output=True, text=True).stdout
+    missing = [l.strip() for l in und.splitlines() if " md::" in l or "mdgemm" in l or " md_" in l]
+    if missing:
+        os.remove(tmp)
+        raise RuntimeError("link left library symbols undefined:\n" + "\n".join(missing))
     os.replace(tmp, out)
     if verbose:
         print("built", out)
@@ -69,5 +94,5 @@ def build(verbose=True, defines=(), out=OUT, build_dir=BUILD):
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -8,7 +8,7 @@
 namespace md {
 
 // Lowering of a domain case onto one real product (Figure "mixeddom",
-// Section 3.2).  The real product is C' (M' x N') += A' (M' x K') B' (K' x N'):
+// Section 4.2).  The real product is C' (M' x N') += A' (M' x K') B' (K' x N'):
 //   mdbl: M' = 2m -- C and A complex: Re/Im of A and C become separate rows
 //         (case 2ac; in case 3 together with kdbl this is the 1e/1r pairing
 //         of Eq. 1mc);
@@ -60,7 +60,7 @@ struct GemmArgs {
                             // operation, another m x n array of C's type and ldc otherwise
     int64_t lda, ldb, ldc;  // in elements of each operand's own type
     int64_t rsa, rsb, rsc;  // element stride along a stored column: 1, except for general
-                            // storage (Section 2 row and column strides), which only the
+                            // storage (Section 3 row and column strides), which only the
                             // component-wise loads and their epilogue take
     int64_t m, n, k;
     int a_dbl, b_dbl, c_dbl;  // storage precision is double

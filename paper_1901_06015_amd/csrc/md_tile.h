@@ -7,7 +7,7 @@
 //   1. cast-on-pack: A and B tiles are read from HBM in their storage type
 //      with 16-byte loads, converted to the computation type in registers
 //      (float -> double exact, double -> float round-to-nearest-even: the
-//      typecasting pack of Section 4) and written to LDS already in the layout
+//      typecasting pack of Section 5) and written to LDS already in the layout
 //      of the real product: complex elements are split into their parts, parts
 //      that cannot reach C are dropped, conjugation flips a sign, and case 3
 //      writes A in the 1e arrangement of Eq. 1mc (each complex element becomes
@@ -21,7 +21,7 @@
 //   3. an epilogue that applies alpha (cast to the computation precision) and
 //      beta (cast to C's storage precision), forms beta*C + alpha*AB in the
 //      wider of the computation and C precisions, and rounds once to C's
-//      storage type (Sections 4.1.3 and 6.1).
+//      storage type (Sections 5.1.3 and 7.1).
 //
 // LDS layout follows each operand's orientation in HBM so that the staging
 // writes are 16-byte vectors without bank conflicts: an operand contiguous
@@ -502,10 +502,18 @@ __device__ __forceinline__ void update_real(const GemmArgs &g, int64_t i, int64_
     const int64_t off = c_offset<GS>(g, i, j);
     const T ax = (T)g.alpha_re;
     if (HC && g.c_half) {
-        // beta is already binary16; the update in double, one rounding to binary16
+        // beta is already binary16, so beta*C is exact in the computation
+        // type; the update is formed exactly and rounded once to binary16
+        // (in double for the double precision, else a round-to-odd float)
         _Float16 *c = (_Float16 *)g.C;
-        const double t = (double)(ax * acc);
-        c[off] = half_rn(g.beta_zero ? t : fma(g.beta_re, (double)((const _Float16 *)g.Cin)[off], t));
+        const T t = ax * acc;
+        if (g.beta_zero) {
+            c[off] = half_rn(t);
+        } else {
+            const T bc = (T)g.beta_re * (T)((const _Float16 *)g.Cin)[off];
+            if constexpr (sizeof(T) == 8) c[off] = half_rn(bc + t);
+            else c[off] = (_Float16)add_rto(bc, t);
+        }
         return;
     }
     if (g.c_dbl) {
@@ -549,20 +557,31 @@ __device__ __forceinline__ void update_cplx(const GemmArgs &g, int64_t i, int64_
     const int64_t off = 2 * c_offset<GS>(g, i, j);
     const T ar = (T)g.alpha_re, ai = (T)g.alpha_im;
     if (HC && g.c_half) {
-        // alpha*AB in the computation precision, the beta update in double,
-        // one rounding to binary16 per part
+        // alpha*AB in the computation precision; beta and C are binary16, so
+        // each product beta_x * c_y is exact in the computation type and the
+        // update of each part (up to three terms) is formed exactly and
+        // rounded once to binary16 (in double for the double precision, else
+        // through a round-to-odd float)
         _Float16 *c = (_Float16 *)g.C + off;
         const _Float16 *cin = (const _Float16 *)g.Cin + off;
-        const double tr = (double)fma(ar, re, -(ai * im));
-        const double ti = (double)fma(ar, im, ai * re);
-        double rr = tr, ri = ti;
-        if (!g.beta_zero) {
-            const double br = g.beta_re, bi = g.beta_im, cr = (double)cin[0], ci = (double)cin[1];
-            rr = fma(br, cr, fma(-bi, ci, tr));
-            ri = fma(br, ci, fma(bi, cr, ti));
+        const T tr = fma(ar, re, -(ai * im));
+        const T ti = fma(ar, im, ai * re);
+        if (g.beta_zero) {
+            c[0] = half_rn(tr);
+            c[1] = half_rn(ti);
+            return;
         }
-        c[0] = half_rn(rr);
-        c[1] = half_rn(ri);
+        const T br = (T)g.beta_re, bi = (T)g.beta_im, cr = (T)cin[0], ci = (T)cin[1];
+        if constexpr (sizeof(T) == 8) {
+            c[0] = half_rn(fma(br, cr, fma(-bi, ci, tr)));
+            c[1] = half_rn(fma(br, ci, fma(bi, cr, ti)));
+        } else if (bi == 0.0f) {
+            c[0] = (_Float16)add_rto(br * cr, tr);
+            c[1] = (_Float16)add_rto(br * ci, ti);
+        } else {
+            c[0] = (_Float16)add3_rto(br * cr, -(bi * ci), tr);
+            c[1] = (_Float16)add3_rto(br * ci, bi * cr, ti);
+        }
         return;
     }
     if (g.c_dbl) {

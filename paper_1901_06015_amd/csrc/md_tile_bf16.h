@@ -7,8 +7,11 @@
 // a - hi is exact in FP32) and writes hi and lo to two LDS planes.  Each
 // product of the real product is formed from three bf16 products,
 //     a*b ~ hi_a*hi_b + hi_a*lo_b + lo_a*hi_b,
-// accumulated in FP32 by v_mfma_f32_16x16x32_bf16 (the dropped lo_a*lo_b and
-// the split residuals are below 2^-16 |a||b| per term).  The lowering of the
+// accumulated in FP32 by v_mfma_f32_16x16x32_bf16.  bf16 keeps 8 significant
+// bits, so |lo| <= 2^-8 |a| and a - hi - lo <= 2^-16 |a|: the dropped
+// lo_a*lo_b and the two residuals leave up to about 3 * 2^-16 |a||b| per
+// product, inside the single-precision bound 4 k u_s |a||b| from k ~ 192 on
+// (below that the split's term is the larger one).  The lowering of the
 // domain cases, the staging loads and the epilogue are those of md_tile.h with
 // T = float.  This precision form is an addition of this library, not of the
 // paper.

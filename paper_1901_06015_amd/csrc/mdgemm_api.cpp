@@ -1,6 +1,6 @@
 // mdgemm_api.cpp -- the C ABI of libmdgemm: argument validation, domain-case
 // classification (Figure "mixeddom"), the computation-precision and scalar
-// policies (Sections 4.1 and 6), quick returns, and dispatch to the kernels.
+// policies (Sections 5.1 and 7), quick returns, and dispatch to the kernels.
 #include <stdio.h>
 #include <string.h>
 
@@ -15,7 +15,7 @@ int norm_trans(char t) {
     case 'N': case 'n': return 0;
     case 'T': case 't': return 1;
     case 'C': case 'c': return 2;
-    case 'R': case 'r': return 3;  // conjugate without transposing (Section 2's hypothetical API)
+    case 'R': case 'r': return 3;  // conjugate without transposing (Section 3's hypothetical API)
     }
     return -1;
 }
@@ -74,6 +74,10 @@ int storage_view(int64_t rows, int64_t cols, int64_t rs, int64_t cs, View *v) {
 bool dt_cplx(int dt) { return dt == MD_C || dt == MD_Z || dt == MD_HC; }
 bool dt_dbl(int dt) { return dt == MD_D || dt == MD_Z; }
 bool dt_half(int dt) { return dt == MD_H || dt == MD_HC; }
+// bytes of one stored element
+int64_t dt_bytes(int dt) {
+    return dt == MD_Z ? 16 : (dt == MD_D || dt == MD_C) ? 8 : dt == MD_S ? 4 : dt == MD_HC ? 4 : 2;
+}
 int64_t max1(int64_t v) { return v > 1 ? v : 1; }
 
 }  // namespace
@@ -110,14 +114,14 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     const bool literal = comp != MD_COMP_DEFAULT && (comp & MD_COMP_LITERAL_ALPHA);
     if (literal) comp &= ~MD_COMP_LITERAL_ALPHA;
 
-    // Section 4.1.1: the computation precision defaults to C's storage precision.
+    // Section 5.1.1: the computation precision defaults to C's storage precision.
     if (comp == MD_COMP_DEFAULT) comp = dt_dbl(dtc) ? MD_COMP_D : (dt_half(dtc) ? MD_COMP_H : MD_COMP_S);
     d.prec = comp == MD_COMP_D ? PREC_D
            : comp == MD_COMP_S ? PREC_S
            : comp == MD_COMP_H ? PREC_H : PREC_BF16X3;
     d.cs = classify(dtc, dta, dtb);
 
-    // Section 6.2: Im(alpha) is projected away in case 0, used in case 3 and
+    // Section 7.2: Im(alpha) is projected away in case 0, used in case 3 and
     // refused in the six mixed cases -- unless the caller asks for the literal
     // interpretation: then a complex C takes the complex alpha in the epilogue,
     // and for a real C the complex operand is staged as alpha times itself
@@ -135,9 +139,9 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
             are = 1.0; aim = 0.0;
         }
     }
-    // Section 6.2: Im(beta) cannot change a real C.
+    // Section 7.2: Im(beta) cannot change a real C.
     double bre = beta.re, bim = dt_cplx(dtc) ? beta.im : 0.0;
-    // Section 6.1 option (1): beta takes C's storage precision.
+    // Section 7.1 option (1): beta takes C's storage precision.
     if (dt_half(dtc)) { bre = (double)(_Float16)bre; bim = (double)(_Float16)bim; }
     else if (!dt_dbl(dtc)) { bre = (double)(float)bre; bim = (double)(float)bim; }
 
@@ -155,12 +159,26 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     // contiguous along k whose columns are not a whole number of chunks is
     // "ragged": the components a chunk reads past a column's end are zeroed
     // after the load (Stage::load_fast).
-    // They address a tile with 32-bit offsets from its origin: 128 columns of
-    // the operand must span less than 2 GiB.
     const int wa = dt_cplx(dta) ? 2 : 1, wb = dt_cplx(dtb) ? 2 : 1;
     // components per 16-byte chunk
     const int cwa = dt_dbl(dta) ? 2 : (dt_half(dta) ? 8 : 4), cwb = dt_dbl(dtb) ? 2 : (dt_half(dtb) ? 8 : 4);
-    const int64_t max_ld = ((int64_t)1 << 31) / (128 * 16) - 64;
+    // They address an operand tile with 32-bit byte offsets from its origin:
+    // the stored columns the fast tile spans (its k extent for an operand
+    // stored along m or n, its m or n extent for one stored along k), ld
+    // elements apart, plus the reach of a chunk inside its column, must stay
+    // below 2 GiB.  The tile is the one the fast kernel of this precision and
+    // case would run, so a wider tile lowers the limit.
+    int fbm, fbn, fbk;
+    tile_shape(d.prec, d.cs, true, &fbm, &fbn, &fbk);
+    const Lowering L0 = lower_case(d.cs);
+    auto fast_ld_ok = [&](bool is_a, int dt, int tr, int64_t ld) {
+        const bool mn_contig = is_a ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2);
+        const int64_t tmn = is_a ? fbm / (L0.mdbl ? 2 : 1) : fbn / (L0.ndbl ? 2 : 1);
+        const int64_t tk = fbk / (L0.kdbl ? 2 : 1);
+        const int64_t cols = mn_contig ? tk : tmn;
+        const int64_t reach = 4096;  // a chunk's offset inside its column: < 256 elements of 16 bytes
+        return ld < ((((int64_t)1 << 31) - reach) / (cols * dt_bytes(dt)));
+    };
     // General storage (an element stride along the column, for any operand)
     // takes the component-wise path.  Binary16 operands have fast kernels when
     // both A and B are binary16 and the precision is single or half, with
@@ -170,8 +188,8 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     const bool half_pair = dt_half(dta) && dt_half(dtb) && (d.prec == PREC_S || d.prec == PREC_H) &&
                            (lda * wa) % 2 == 0 && (ldb * wb) % 2 == 0;
     const bool ha_ok = !dt_half(dta) || half_pair, hb_ok = !dt_half(dtb) || half_pair;
-    g.a_vec = ((uintptr_t)A % 4 == 0) && lda < max_ld && rsa == 1 && plain_c && ha_ok;
-    g.b_vec = ((uintptr_t)B % 4 == 0) && ldb < max_ld && rsb == 1 && plain_c && hb_ok;
+    g.a_vec = ((uintptr_t)A % 4 == 0) && fast_ld_ok(true, dta, ta, lda) && rsa == 1 && plain_c && ha_ok;
+    g.b_vec = ((uintptr_t)B % 4 == 0) && fast_ld_ok(false, dtb, tb, ldb) && rsb == 1 && plain_c && hb_ok;
     g.a_ragged = (ta == 1 || ta == 2) && (k * wa) % cwa != 0;
     g.b_ragged = (tb == 0 || tb == 3) && (k * wb) % cwb != 0;
     g.alpha_re = are; g.alpha_im = aim;

@@ -179,8 +179,8 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
     }
     const int ntiles = (int)tiles.size();
     const int grid = std::min(ntiles, num_cu() * GROUPED_OCC);
-    hipLaunchKernelGGL(md_grouped_kernel, dim3(grid), dim3(NT), 0, s, (const GDesc *)(dev + hdr_bytes),
-                       (const GTile *)(dev + hdr_bytes + desc_bytes), ntiles, (int *)dev);
+    launch_grouped_kernel(grid, s, (const GDesc *)(dev + hdr_bytes), (const GTile *)(dev + hdr_bytes + desc_bytes),
+                          ntiles, (int *)dev);
     const hipError_t le = hipGetLastError();
     if (!ws) (void)hipFreeAsync(dev, s);
     if (le != hipSuccess) return MD_ERR_HIP;

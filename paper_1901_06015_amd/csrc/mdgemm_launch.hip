@@ -49,19 +49,20 @@ __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
         const int64_t i = t % g.m, j = t / g.m;
         const int64_t off = i * g.rsc + j * g.ldc;
         if (g.c_half) {
-            // beta is already binary16: products of two binary16 values are
-            // exact in double, their sum nearly always; one rounding to binary16
+            // beta is already binary16: a product of two binary16 values is
+            // exact in float; a sum of two is rounded to odd in float, then
+            // once to binary16 (one rounding)
             _Float16 *c = (_Float16 *)g.C + (g.c_cplx ? 2 * off : off);
             const _Float16 *cin = (const _Float16 *)g.Cin + (g.c_cplx ? 2 * off : off);
             if (g.beta_zero) {
                 c[0] = (_Float16)0.0f;
                 if (g.c_cplx) c[1] = (_Float16)0.0f;
             } else if (g.c_cplx) {
-                const double br = g.beta_re, bi = g.beta_im, cr = (double)cin[0], ci = (double)cin[1];
-                c[0] = half_rn(br * cr - bi * ci);
-                c[1] = half_rn(br * ci + bi * cr);
+                const float br = (float)g.beta_re, bi = (float)g.beta_im, cr = (float)cin[0], ci = (float)cin[1];
+                c[0] = (_Float16)add_rto(br * cr, -(bi * ci));
+                c[1] = (_Float16)add_rto(br * ci, bi * cr);
             } else {
-                c[0] = half_rn(g.beta_re * (double)cin[0]);
+                c[0] = (_Float16)((float)g.beta_re * (float)cin[0]);
             }
         } else if (g.c_cplx) {
             if (g.c_dbl) {
@@ -147,15 +148,19 @@ static int split_count(int prec, int cs, const GemmArgs &a, int64_t tiles) {
 }
 
 // Split workspaces: one per (device, stream), grown on demand and kept for the
-// life of the process.  Work on one stream runs in order, so the calls that
-// share a workspace never overlap; different streams have their own.  Growth
-// frees the old buffer in stream order (after the work already enqueued).
+// life of the process (at most about 100 MB each: S x tiles <= CUs + tiles
+// workgroup tiles of partial (re, im) pairs).  Work on one stream runs in
+// order, so products that share a workspace never overlap on the device, as
+// long as each product's two launches (split kernel, reduction) are enqueued
+// back to back: the caller holds g_ws_mu from taking the workspace until both
+// are enqueued, so two host threads on one stream cannot interleave them.
+// Growth frees the old buffer in stream order (after the work already
+// enqueued, which includes every earlier user's reduction).
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_ws;
-static void *split_workspace(hipStream_t s, size_t bytes) {
+static void *split_workspace_locked(hipStream_t s, size_t bytes) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lk(g_ws_mu);
     auto &e = g_ws[std::make_pair(dev, s)];
     if (e.first && e.second >= bytes) return e.first;
     void *p = nullptr;
@@ -167,6 +172,19 @@ static void *split_workspace(hipStream_t s, size_t bytes) {
     e.first = p;
     e.second = bytes;
     return p;
+}
+
+// Launch the product kernel and, for a split product, the reduction that
+// finishes it (a.part must hold a.splits x m x n partial pairs).
+static void enqueue_product(int prec, int cs, const GemmArgs &a, hipStream_t s, int64_t tiles) {
+    kParts[prec][cs](a, s, (unsigned)(tiles * a.splits));
+    if (a.splits > 1) {
+        const int64_t total = a.m * a.n;
+        int64_t blocks = (total + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        if (prec == PREC_D) hipLaunchKernelGGL(md_split_reduce<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(md_split_reduce<float>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    }
 }
 
 int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg) {
@@ -181,17 +199,13 @@ int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg)
     if (a.splits > 1) {
         const size_t esz = prec == PREC_D ? sizeof(double) : sizeof(float);
         const size_t bytes = (size_t)a.splits * (size_t)a.m * (size_t)a.n * 2 * esz;
+        std::lock_guard<std::mutex> lk(g_ws_mu);
         // the stream's workspace; without it the product runs unsplit
-        a.part = split_workspace(s, bytes);
+        a.part = split_workspace_locked(s, bytes);
         if (!a.part) a.splits = 1;
-    }
-    kParts[prec][cs](a, s, (unsigned)(n * a.splits));
-    if (a.splits > 1) {
-        const int64_t total = a.m * a.n;
-        int64_t blocks = (total + 255) / 256;
-        if (blocks > 4096) blocks = 4096;
-        if (prec == PREC_D) hipLaunchKernelGGL(md_split_reduce<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(md_split_reduce<float>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        enqueue_product(prec, cs, a, s, n);
+    } else {
+        enqueue_product(prec, cs, a, s, n);
     }
     return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
 }

@@ -11,14 +11,14 @@ What fixes what (the paper is Van Zee, Parikh, van de Geijn, FLAME WN #89):
   * pin_same_type                   -- same-type combinations are an ordinary
                                        GEMM (Section 1): numpy.matmul
   * pin_domain_identities           -- each case's interpretation in Figure
-                                       "mixeddom" / Section 3.2, written with
+                                       "mixeddom" / Section 4.2, written with
                                        real numpy products of the parts
   * pin_exact_integers              -- exact integer arithmetic (numpy int64)
   * pin_exact_rational              -- Python Fractions on tiny float inputs:
                                        the oracle's own error stays within the
                                        classical gamma_{2k} dot-product bound
-  * pin_1m_equations                -- Eq. (1mc) and Eq. (1mr) of Section 3.1
-  * pin_scalars                     -- Section 6 scalar policies (golden
+  * pin_1m_equations                -- Eq. (1mc) and Eq. (1mr) of Section 4.1
+  * pin_scalars                     -- Section 7 scalar policies (golden
                                        fixture) and BLAS quick-return rules
   * pin_transpose                   -- Section 1's op(A) = A^T / A^H variants
   * pin_bound_term                  -- the bound term sum_p |op(A)_ip||op(B)_pj|
@@ -65,7 +65,7 @@ def _dom_tags(is_cplx):
 
 def _op(X, rows, cols, trans):
     """op(X) as a complex128 array of the promoted stored values; "R" is the
-    conjugate without transposition of Section 2's hypothetical API."""
+    conjugate without transposition of Section 3's hypothetical API."""
     M = inputs.to_complex128(X[:rows, :cols])
     if trans == "N":
         return M
@@ -230,7 +230,7 @@ def _frac(x):
 def pin_exact_rational(o):
     """Exact rational evaluation of the definition on tiny float inputs.  A plain
     recursive FP64 sum of k complex products has error below gamma_{2k+2} * g
-    (Higham, Accuracy and Stability, Section 3.1), so anything larger is a bug."""
+    (Higham, Accuracy and Stability, Section 4.1), so anything larger is a bug."""
     fails = []
     u = 2.0 ** -53
     for tc, ta_, tb_ in (("z", "c", "d"), ("d", "z", "z"), ("c", "s", "z"), ("z", "z", "z"),
@@ -274,7 +274,7 @@ def pin_1m_equations(o):
     """Eq. (1mc): with C column-stored, a real product of A in the 1e format
     (2m x 2k) and B in the 1r format (2k x n) is C (2m x n, re/im rows
     interleaved).  Eq. (1mr): A in 1r (m x 2k) times B in 1e (2k x 2n) gives C
-    with re/im columns interleaved.  Example size of Section 3.1: m=3, n=4, k=2,
+    with re/im columns interleaved.  Example size of Section 4.1: m=3, n=4, k=2,
     plus one larger size."""
     fails = []
     for m, n, k in ((3, 4, 2), (7, 5, 6)):
@@ -319,7 +319,7 @@ def pin_scalars(o):
     for tc, ta_, tb_ in itertools.product(("s", "z"), ("d", "c"), ("s", "z")):
         case = o.case(tc, ta_, tb_)
         A, B, C, _, _ = _operands(ta_, tb_, tc, m, n, k, "N", "N", seed=61)
-        # Section 6.2: complex alpha
+        # Section 7.2: complex alpha
         st, got, _ = _call(o, "N", "N", m, n, k, 1.5 + 0.5j, A, ta_, B, tb_, 1.0, C, tc)
         if policy[case] != (st == 0):
             fails.append("alpha policy case %s status %d" % (case, st))
@@ -327,7 +327,7 @@ def pin_scalars(o):
             st2, ref, _ = _call(o, "N", "N", m, n, k, 1.5, A, ta_, B, tb_, 1.0, C, tc)
             if not np.array_equal(got, ref):
                 fails.append("case 0 alpha not projected")
-        # Section 6.2: Im(beta) cannot change a real C
+        # Section 7.2: Im(beta) cannot change a real C
         if tc == "s":
             st1, r1, _ = _call(o, "N", "N", m, n, k, 1.0, A, ta_, B, tb_, 0.5 + 7j, C, tc)
             st2, r2, _ = _call(o, "N", "N", m, n, k, 1.0, A, ta_, B, tb_, 0.5, C, tc)
@@ -358,7 +358,7 @@ def pin_scalars(o):
         st, r, _ = o.gemm("N", "N", m, n, 0, 2.0, An, ta_, m, B, tb_, 1, -0.5, C, tc, m)
         if st != 0 or not np.array_equal(r, expect):
             fails.append("k=0 case %s" % case)
-    # Section 3.2 case 1c: AB reaches only Re(C); Im(C) is beta*Im(C) exactly
+    # Section 4.2 case 1c: AB reaches only Re(C); Im(C) is beta*Im(C) exactly
     for tc in ("c", "z"):
         A, B, C, _, _ = _operands("d", "s", tc, m, n, k, "N", "N", seed=71)
         st, r, _ = _call(o, "N", "N", m, n, k, 1.5, A, "d", B, "s", -0.5, C, tc)
@@ -400,7 +400,7 @@ def _store(X, rows, cols, rs, cs, pad=777.25):
 
 
 def pin_strides(o):
-    """Section 2's row and column strides: the same logical operands stored
+    """Section 3's row and column strides: the same logical operands stored
     column-major, row-major and in general storage (neither stride 1) give
     numpy's product for homogeneous storage, and bitwise the column-major
     result for mixed storage."""
@@ -438,7 +438,7 @@ def pin_strides(o):
 
 
 def pin_literal_alpha(o):
-    """Section 6.2's literal interpretation (all five operands in their own
+    """Section 7.2's literal interpretation (all five operands in their own
     domains): with Im(alpha) != 0 every one of the 64 storage combinations
     equals the homogeneous complex product alpha*op(A)*op(B) + beta*C formed by
     numpy, projected to Re for a real C -- exactly for integer inputs; and for

@@ -81,7 +81,7 @@ def test_alpha_policy():
 
 def test_half_storage_plans():
     """Binary16 storage (h, hc): the domain case follows the domains, the
-    default computation precision of a half C is half (Section 4.1.1: C's
+    default computation precision of a half C is half (Section 5.1.1: C's
     precision); a half C takes the fast kernels, binary16 operands take them
     when both are binary16 and the precision is single or half, and the half
     computation precision keeps them for s/d/c/z storage."""
@@ -106,7 +106,7 @@ def test_half_storage_plans():
 
 
 def test_literal_alpha_flag():
-    """MD_COMP_LITERAL_ALPHA lifts Section 6.2's refusal of Im(alpha) in the
+    """MD_COMP_LITERAL_ALPHA lifts Section 7.2's refusal of Im(alpha) in the
     six mixed cases; it needs an explicit precision and changes no flop count."""
     for tc, ta, tb in itertools.product(("s", "c"), ("d", "z"), ("s", "c")):
         st0, p0 = _plan(tc, ta, tb, comp="d", alpha=1.0 + 0.5j)
@@ -168,7 +168,7 @@ def test_argument_errors():
 
 
 def test_conjugate_without_transpose_plans_like_n():
-    """'R' (Section 2) reads A or B as stored, like 'N': same shapes, same
+    """'R' (Section 3) reads A or B as stored, like 'N': same shapes, same
     leading-dimension rule, same kernel family."""
     for tc, ta, tb in (("z", "c", "z"), ("c", "z", "s"), ("d", "d", "d")):
         stn, pn = _plan(tc, ta, tb, transa="N", transb="N")
@@ -256,3 +256,26 @@ def test_server_config_is_validated_before_any_device_call():
             assert e.status == _lib.MD_ERR_STATE, kw
         else:
             raise AssertionError("invalid configuration accepted: %r" % kw)
+
+
+@pytest.mark.parametrize("comp,tile_cols", [("h", 256), ("d", 128), ("s", 128), ("bf16x3", 128)])
+def test_fast_path_leading_dimension_limit_follows_the_tile(comp, tile_cols):
+    """The fast kernels address an operand tile with 32-bit byte offsets: the
+    stored columns the tile spans, ld elements apart, must stay below 2 GiB.
+    A z operand stored along k spans the tile's m (or n) extent: 256 columns
+    under the half precision's 256 x 256 tiles, 128 otherwise.  Just below the
+    limit the fast kernel runs; beyond it the component-wise kernel (64-bit
+    addressing), whatever the tile."""
+    limit = ((1 << 31) - 4096) // (tile_cols * 16)
+    for ld, want_fast in ((limit - 1, True), (limit + 1, False), (600000, 600000 < limit)):
+        # B z stored along k ('N'), case 2ab (C real, A and B complex)
+        st, p = _plan("d", "z", "z", comp, m=300, n=300, k=64, ldb=ld)
+        assert st == 0, st
+        assert ("generic" not in p["kernel"]) == want_fast, (comp, ld, p["kernel"])
+        # A z stored along k ('T')
+        st, p = _plan("d", "z", "z", comp, m=300, n=300, k=64, transa="T", lda=ld)
+        assert st == 0, st
+        assert ("generic" not in p["kernel"]) == want_fast, (comp, ld, p["kernel"])
+    # along m the tile spans only its k extent: a large ld stays fast
+    st, p = _plan("d", "z", "z", comp, m=300, n=300, k=64, lda=limit + 1)
+    assert st == 0 and "generic" not in p["kernel"], p["kernel"]

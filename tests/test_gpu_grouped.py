@@ -39,8 +39,6 @@ def make_entries(count, seed, lo=1, hi=300, dist="uniform", comps=("s", "d", "bf
         tc, ta, tb = (TAGS[j] for j in rng.integers(0, 4, 3))
         comp = comps[int(rng.integers(0, len(comps)))]
         m, n, k = (int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi + 1))))) for _ in range(3))
-        if comp == "bf16x3" and dist != "int":
-            k = max(k, 96)  # the split's error fits the single-precision bound from k ~ 96 on
         transa, transb = "NTCR"[int(rng.integers(0, 4))], "NTCR"[int(rng.integers(0, 4))]
         case = oracle.get().case(tc, ta, tb)
         alpha = 0.75 - 0.5j if case == "3" else 1.5

@@ -54,7 +54,7 @@ def test_all_storage_combinations(tc, comp):
 @pytest.mark.parametrize("transa,transb", list(itertools.product("NTCR", "NTCR")))
 def test_transpose_variants(transa, transb):
     """The nine op(A), op(B) combinations of Section 1 plus conjugation
-    without transposition (R, Section 2), on a combination of every domain
+    without transposition (R, Section 3), on a combination of every domain
     case."""
     combos = ["ddd", "sdc", "dzs", "scz", "csd", "zdz", "czs", "zcz"]
     for i, cab in enumerate(combos):
@@ -98,7 +98,7 @@ def test_unaligned_leading_dimensions():
 
 
 def test_complex_scalars_case3():
-    """Case 3 uses a complex alpha and a complex beta (Section 6.2)."""
+    """Case 3 uses a complex alpha and a complex beta (Section 7.2)."""
     for cab in ("zzz", "ccc", "zcz", "czc"):
         assert oracle.get().case(cab[0], cab[1], cab[2]) == "3"
         for comp in ("s", "d"):
@@ -196,10 +196,12 @@ def test_bf16x3_exact_inputs_bitwise(tc):
 
 @pytest.mark.parametrize("tc", TAGS)
 def test_bf16x3_within_single_precision_bound(tc):
-    """Random inputs at k >= 96, where the split's per-term error (below
-    3*2^-18 |a||b|) plus FP32 accumulation stays inside 4 k u_s (|A||B|)."""
-    for ta, tb in itertools.product(TAGS, TAGS):
-        one(tc, ta, tb, 150, 140, 130, "bf16x3")
+    """Random inputs at k from 16 to 130: within 4 k u_s (|A||B|) plus the
+    split's per-product term 3 * 2^-16 |a||b| (BF16X3_SPLIT), so the check
+    holds worst-case at every k, below the k ~ 192 where 4 k u_s alone would
+    cover the split."""
+    for i, (ta, tb) in enumerate(itertools.product(TAGS, TAGS)):
+        one(tc, ta, tb, 150, 140, (16, 47, 130)[i % 3], "bf16x3")
 
 
 def test_bf16x3_transposes_and_loguniform():
@@ -212,7 +214,7 @@ def test_bf16x3_transposes_and_loguniform():
 
 @pytest.mark.parametrize("layouts", list(itertools.product(("col", "row", "gen", "genr"), repeat=3)))
 def test_row_and_column_strides(layouts):
-    """Section 2's row and column strides: every operand stored by columns, by
+    """Section 3's row and column strides: every operand stored by columns, by
     rows (with spare elements between columns/rows) or in general storage
     (neither stride 1), on a combination of every domain case and all four
     ops; elements outside C's block are never written."""
@@ -297,7 +299,7 @@ MIXED = {"1a": ("scs", "dcd", "szs"), "1b": ("ssc", "dsz", "sdc"), "1c": ("css",
 @pytest.mark.parametrize("case", sorted(MIXED))
 def test_literal_complex_alpha(case):
     """MD_COMP_LITERAL_ALPHA: Im(alpha) != 0 in the six mixed cases, applied as
-    the literal interpretation of Section 6.2 (the oracle's literal variant),
+    the literal interpretation of Section 7.2 (the oracle's literal variant),
     in both precisions and BF16x3, with every op on both operands, on the fast
     path, the ragged/unaligned path and the component-wise path."""
     alpha, beta = 0.75 - 0.5j, -0.5 + 0.25j
@@ -492,8 +494,24 @@ def test_split_k_exact_and_strided():
 
 
 def test_huge_leading_dimension_generic_path():
-    """A leading dimension of 2^20 or more keeps the kernels' 32-bit tile
-    offsets from fitting: the component-wise path takes over, with the same
-    result."""
+    """A stored along m with a leading dimension above 2^20: its fast tile
+    spans only its k extent of columns, so the 32-bit tile offsets still fit
+    and the result is the same as at any other ld."""
     for cab, comp in (("zcd", "d"), ("sds", "s")):
         one(cab[0], cab[1], cab[2], 40, 24, 8, comp, pad_a=(1 << 20) - 40 + 8)
+
+
+@pytest.mark.parametrize("comp", ["h", "d"])
+def test_large_ld_operand_stored_along_k(comp):
+    """B (z, 'N') stored along k with ld = 600000 spans one column per n of
+    its tile: under the half precision's 256-wide tiles, 240 columns of
+    600000 x 16 bytes pass 2 GiB, so the planner must leave the 32-bit fast
+    kernels (Section 2.2.1 storage: any ld >= rows is valid and must not change
+    the result).  Under the double precision (128-wide tiles) the fast kernel
+    still fits and runs.  Case 1b: C and A single real, B double complex."""
+    m, n, k, ldb = 64, 240, 40, 600000
+    st, p = _lib.mdgemm_plan("N", "N", m, n, k, 1.5, 0x1000, "s", m, 0x1000, "z", ldb, -0.5, 0x1000, "s", m, comp)
+    assert st == 0
+    assert ("generic" in p["kernel"]) == (comp == "h"), p["kernel"]
+    say("large ld along k:", p["kernel"])
+    one("s", "s", "z", m, n, k, comp, pad_b=ldb - k)

@@ -41,8 +41,6 @@ def make_requests(srv, count, seed, hi=400, big_every=8):
             m, n, k = 512, 384, 640
         else:
             m, n, k = (int(np.floor(np.exp(rng.uniform(np.log(8), np.log(hi))))) for _ in range(3))
-        if comp == "bf16x3":
-            k = max(k, 96)
         transa, transb = "NTR"[int(rng.integers(0, 3))], "NCR"[int(rng.integers(0, 3))]
         ar, ac = (m, k) if transa in "NR" else (k, m)
         br, bc = (k, n) if transb in "NR" else (n, k)
@@ -131,7 +129,7 @@ def test_invalid_requests_refused_server_keeps_serving():
         assert st != 0
         st, _ = srv.submit("N", "N", r["m"], r["n"], r["k"], 1.0, 987654, r["hb"], 0.0, None, r["tc"], "s")
         assert st == _lib.MD_ERR_STATE
-        # Im(alpha) != 0 in a mixed case (Section 6.2)
+        # Im(alpha) != 0 in a mixed case (Section 7.2)
         A = srv.put(inputs.matrix(16, 16, "c", 1))
         Bh = srv.put(inputs.matrix(16, 16, "s", 2))
         st, _ = srv.submit("N", "N", 16, 16, 16, 1.0 + 1.0j, A, Bh, 0.0, None, "s", "s")
