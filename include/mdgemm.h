@@ -112,6 +112,7 @@ typedef enum {
 #define MD_ERR_BUDGET 3      /* a serving request exceeds the memory budget */
 #define MD_ERR_STATE 4       /* call not valid in the object's current state */
 #define MD_ERR_UNSUPPORTED 5 /* valid request that this build cannot run */
+#define MD_ERR_SCRATCH 6     /* mdgemm_grouped_noalloc: work table larger than its fixed scratch */
 
 /*
  * mdgemm -- one mixed-datatype product.
@@ -227,6 +228,30 @@ typedef struct {
 } md_gemm_desc;
 
 int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream);
+
+/*
+ * mdgemm_grouped_noalloc -- mdgemm_grouped for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, validation, kernels and results,
+ * except:
+ *   - the work table (a 256-byte header holding the tile counter, one
+ *     descriptor per product, 16 bytes per output tile) is uploaded into a
+ *     fixed array of MD_GROUPED_NOALLOC_BYTES that the library holds on each
+ *     GPU it runs on until the process ends, instead of a stream-ordered
+ *     allocation; a table that does not fit returns MD_ERR_SCRATCH and
+ *     enqueues nothing;
+ *   - products that mdgemm_grouped hands to the plain kernels (large leading
+ *     dimensions, binary16, a complex alpha staged into an operand) run
+ *     unsplit, so no split-k workspace is taken.
+ * It calls no hipMalloc, hipFree or other allocating routine (the host copy
+ * of the table is ordinary host memory, consumed by the upload).  Every call
+ * on one GPU shares that GPU's array, which keeps the last call's table:
+ * calls on one stream from one host thread run in order, but calls that
+ * overlap on one GPU (other streams, or host threads sharing a stream) race
+ * on it -- serialise them.
+ */
+#define MD_GROUPED_NOALLOC_BYTES (8u << 20)
+int mdgemm_grouped_noalloc(int64_t count, const md_gemm_desc *descs, void *stream);
 
 /*
  * Tile-shape table of the grouped kernel: for each computation precision

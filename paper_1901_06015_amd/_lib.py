@@ -16,6 +16,8 @@ LIB_PATH = os.environ.get("MDGEMM_LIBRARY", os.path.join(HERE, "libmdgemm.so"))
 MD_S, MD_D, MD_C, MD_Z, MD_H, MD_HC = 0, 1, 2, 3, 4, 5
 MD_COMP_DEFAULT, MD_COMP_S, MD_COMP_D, MD_COMP_S_BF16X3, MD_COMP_H = -1, 0, 1, 2, 3
 MD_OK, MD_ERR_ALPHA_IMAG, MD_ERR_HIP, MD_ERR_BUDGET, MD_ERR_STATE, MD_ERR_UNSUPPORTED = 0, 1, 2, 3, 4, 5
+MD_ERR_SCRATCH = 6
+MD_GROUPED_NOALLOC_BYTES = 8 << 20
 CASE_NAMES = ("0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3")
 DT_TAG = {"s": MD_S, "d": MD_D, "c": MD_C, "z": MD_Z, "h": MD_H, "hc": MD_HC}
 COMP_TAG = {None: MD_COMP_DEFAULT, "default": MD_COMP_DEFAULT, "s": MD_COMP_S, "d": MD_COMP_D,
@@ -68,6 +70,8 @@ def lib():
         L.mdgemm_plan.restype = ci
         L.mdgemm_grouped.argtypes = [i64, ctypes.POINTER(MdGemmDesc), vp]
         L.mdgemm_grouped.restype = ci
+        L.mdgemm_grouped_noalloc.argtypes = [i64, ctypes.POINTER(MdGemmDesc), vp]
+        L.mdgemm_grouped_noalloc.restype = ci
         L.mdgemm_tune_load.argtypes = [ctypes.c_char_p]
         L.mdgemm_tune_load.restype = ci
         L.mdgemm_tune_set.argtypes = [ci, ci, ci, ci]
@@ -149,6 +153,11 @@ def make_desc(transa, transb, m, n, k, alpha, A, dta, lda, B, dtb, ldb, beta, C,
 def mdgemm_grouped(descs, stream=None):
     arr = (MdGemmDesc * len(descs))(*descs)
     return lib().mdgemm_grouped(len(descs), arr, stream)
+
+
+def mdgemm_grouped_noalloc(descs, stream=None):
+    arr = (MdGemmDesc * len(descs))(*descs)
+    return lib().mdgemm_grouped_noalloc(len(descs), arr, stream)
 
 
 def strerror(status):

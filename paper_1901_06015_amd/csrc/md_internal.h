@@ -130,7 +130,9 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
                 int64_t rsa = 1, int64_t rsb = 1, int64_t rsc = 1);
 
 // Host-side launchers (defined in mdgemm_kernels.hip).
-int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out);
+// may_split false: never split k, so nothing is allocated (the split-k
+// workspace is the plain path's only allocation).
+int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out, bool may_split = true);
 int launch_scale(const GemmArgs &a, void *stream);
 void tile_shape(int prec, int cs, bool fast, int *bm, int *bn, int *bk);
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len);
@@ -139,7 +141,7 @@ void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len);
 // C := beta*Cin + alpha*op(A)op(B), where Cin (m x n, C's storage type,
 // leading dimension ldc) is read and C is written; a null c_in means in place.
 // Validation and status codes are mdgemm's / mdgemm_grouped's.
-int gemm_enqueue(const md_gemm_desc &d, const void *c_in, void *stream);
+int gemm_enqueue(const md_gemm_desc &d, const void *c_in, void *stream, bool may_split = true);
 
 // Reusable descriptor-table workspace of one stream that issues grouped
 // launches: page-locked host staging and its device copy, grown on demand.
@@ -149,8 +151,11 @@ struct GroupedWs {
     char *dev = nullptr;
     size_t cap = 0;
 };
+// noalloc: upload the work table into the library's fixed device array
+// (MD_ERR_SCRATCH, nothing enqueued, if it does not fit) and run the
+// products that take the plain kernels unsplit: nothing is allocated.
 int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const *c_in, void *stream,
-                    GroupedWs *ws);
+                    GroupedWs *ws, bool noalloc = false);
 void grouped_ws_release(GroupedWs *ws);
 
 }  // namespace md

@@ -214,23 +214,23 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
 
 namespace {
 
-int run_decision(const Decision &d, void *stream) {
+int run_decision(const Decision &d, void *stream, bool may_split = true) {
     if (d.status != MD_OK) return d.status;
     if (d.quick == 1) return MD_OK;
     if (d.quick == 2) return launch_scale(d.g, stream);
     if ((int64_t)d.g.tiles_m * d.g.tiles_n > 0x7fffffffLL) return MD_ERR_UNSUPPORTED;
-    return launch_gemm(d.prec, d.cs, d.g, stream, nullptr);
+    return launch_gemm(d.prec, d.cs, d.g, stream, nullptr, may_split);
 }
 
 }  // namespace
 
 namespace md {
 
-int gemm_enqueue(const md_gemm_desc &x, const void *c_in, void *stream) {
+int gemm_enqueue(const md_gemm_desc &x, const void *c_in, void *stream, bool may_split) {
     Decision d = decide(x.transa, x.transb, x.m, x.n, x.k, x.alpha, x.A, x.dta, x.lda, x.B, x.dtb, x.ldb,
                         x.beta, x.C, x.dtc, x.ldc, x.comp);
     if (c_in) d.g.Cin = c_in;
-    return run_decision(d, stream);
+    return run_decision(d, stream, may_split);
 }
 
 }  // namespace md
@@ -337,6 +337,8 @@ const char *mdgemm_strerror(int status) {
     case MD_ERR_BUDGET: return "request exceeds the memory budget";
     case MD_ERR_STATE: return "invalid state";
     case MD_ERR_UNSUPPORTED: return "not supported by this build";
+    case MD_ERR_SCRATCH:
+        return "the work table exceeds the fixed scratch of mdgemm_grouped_noalloc (MD_GROUPED_NOALLOC_BYTES)";
     }
     return "unknown status";
 }

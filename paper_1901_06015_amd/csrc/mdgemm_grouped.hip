@@ -44,6 +44,33 @@ int choose_cfg(int prec, int cs, int64_t m_real, int64_t n_real) {
 
 int g_num_cu = 0;
 
+// The work table of mdgemm_grouped_noalloc: a fixed array that every GPU the
+// library runs on holds until the process ends.  In host code the array's
+// name only stands for it: the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// passed to copies and kernels.  Every call on one GPU uses the same array,
+// which keeps the last call's table.
+static __device__ __align__(256) char scratch[MD_GROUPED_NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[MAX_DEVICES];
+
+// Device address of the current device's scratch, or nullptr.
+char *scratch_of_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch[dev] = (char *)p;
+    }
+    return g_scratch[dev];
+}
+
 int num_cu() {
     if (g_num_cu == 0) {
         int dev = 0, v = 0;
@@ -62,7 +89,7 @@ using namespace md;
 namespace md {
 
 int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const *c_in, void *stream,
-                    GroupedWs *ws) {
+                    GroupedWs *ws, bool noalloc) {
     if (count < 0) return -1;
     if (count == 0) return MD_OK;
     if (!descs) return -2;
@@ -127,7 +154,7 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
     if (tiles.size() > 0x7fffffffu) return MD_ERR_UNSUPPORTED;
     auto run_alone = [&]() {
         for (int64_t i : alone) {
-            const int rc = gemm_enqueue(descs[i], c_in ? c_in[i] : nullptr, stream);
+            const int rc = gemm_enqueue(descs[i], c_in ? c_in[i] : nullptr, stream, !noalloc);
             if (rc != MD_OK) return rc;
         }
         return (int)MD_OK;
@@ -142,10 +169,19 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
     const size_t desc_bytes = gd.size() * sizeof(GDesc);
     const size_t tile_bytes = tiles.size() * sizeof(GTile);
     const size_t total = hdr_bytes + desc_bytes + tile_bytes;
+    // the size is checked before any device call
+    if (noalloc && total > MD_GROUPED_NOALLOC_BYTES) return MD_ERR_SCRATCH;
     hipStream_t s = (hipStream_t)stream;
     std::vector<char> tmp;
     char *host = nullptr, *dev = nullptr;
-    if (ws) {
+    if (noalloc) {
+        // the fixed array of this device; the host copy is consumed by the
+        // upload before hipMemcpyAsync returns
+        dev = scratch_of_current_device();
+        if (!dev) return MD_ERR_HIP;
+        tmp.resize(total);
+        host = tmp.data();
+    } else if (ws) {
         // grow the reusable staging: the launch that used it has completed
         if (ws->cap < total) {
             grouped_ws_release(ws);
@@ -174,7 +210,7 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
     GTile *ht = (GTile *)(host + hdr_bytes + desc_bytes);
     for (size_t i = 0; i < order.size(); ++i) ht[i] = tiles[order[i]];
     if (hipMemcpyAsync(dev, host, total, hipMemcpyHostToDevice, s) != hipSuccess) {
-        if (!ws) (void)hipFreeAsync(dev, s);
+        if (!ws && !noalloc) (void)hipFreeAsync(dev, s);
         return MD_ERR_HIP;
     }
     const int ntiles = (int)tiles.size();
@@ -182,7 +218,7 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
     launch_grouped_kernel(grid, s, (const GDesc *)(dev + hdr_bytes), (const GTile *)(dev + hdr_bytes + desc_bytes),
                           ntiles, (int *)dev);
     const hipError_t le = hipGetLastError();
-    if (!ws) (void)hipFreeAsync(dev, s);
+    if (!ws && !noalloc) (void)hipFreeAsync(dev, s);
     if (le != hipSuccess) return MD_ERR_HIP;
     return run_alone();
 }
@@ -202,6 +238,10 @@ extern "C" {
 
 int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream) {
     return md::grouped_enqueue(count, descs, nullptr, stream, nullptr);
+}
+
+int mdgemm_grouped_noalloc(int64_t count, const md_gemm_desc *descs, void *stream) {
+    return md::grouped_enqueue(count, descs, nullptr, stream, nullptr, true);
 }
 
 // Tile-shape table file: one entry per line, "comp case bucket cfg" with comp

@@ -187,14 +187,14 @@ static void enqueue_product(int prec, int cs, const GemmArgs &a, hipStream_t s, 
     }
 }
 
-int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg) {
+int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg, bool may_split) {
     const int64_t n = (int64_t)a0.tiles_m * a0.tiles_n;
     if (wg) *wg = n;
     if (n <= 0) return 0;
     if (prec < PREC_S || prec > PREC_H || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     GemmArgs a = a0;
-    a.splits = split_count(prec, cs, a0, n);
+    a.splits = may_split ? split_count(prec, cs, a0, n) : 1;
     a.part = nullptr;
     if (a.splits > 1) {
         const size_t esz = prec == PREC_D ? sizeof(double) : sizeof(float);

@@ -279,3 +279,16 @@ def test_fast_path_leading_dimension_limit_follows_the_tile(comp, tile_cols):
     # along m the tile spans only its k extent: a large ld stays fast
     st, p = _plan("d", "z", "z", comp, m=300, n=300, k=64, lda=limit + 1)
     assert st == 0 and "generic" not in p["kernel"], p["kernel"]
+
+
+def test_grouped_noalloc_rejects_an_oversized_table():
+    """mdgemm_grouped_noalloc keeps its work table in a fixed device array of
+    MD_GROUPED_NOALLOC_BYTES; a table that does not fit (here 40000 one-tile
+    products, about 270 bytes each) is refused with MD_ERR_SCRATCH before any
+    device call, so this runs without a GPU."""
+    count = 40000
+    descs = [_lib.make_desc("N", "N", 8, 8, 8, 1.0, 0x1000, "s", 8, 0x1000, "s", 8, 0.0, 0x1000, "s", 8, "s")
+             for _ in range(count)]
+    st = _lib.mdgemm_grouped_noalloc(descs, None)
+    assert st == _lib.MD_ERR_SCRATCH, st
+    assert "scratch" in _lib.strerror(st)
