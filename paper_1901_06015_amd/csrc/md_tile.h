@@ -87,9 +87,12 @@ template <> struct WideM<double> : TCfg<double, 256, 128, 16, 2, 4, 2> {};
 template <> struct WideM<float> : TCfg<float, 256, 128, 32, 2, 4, 2> {};
 // Deep configuration: the default 128 x 128 tile split over 8 waves of
 // 64 x 32, four waves per SIMD (128 registers per lane).
+#ifndef MD_DEEP_OCC
+#define MD_DEEP_OCC 4
+#endif
 template <class T> struct Deep;
-template <> struct Deep<double> : TCfg<double, 128, 128, 16, 4, 2, 4> {};
-template <> struct Deep<float> : TCfg<float, 128, 128, 32, 4, 2, 4> {};
+template <> struct Deep<double> : TCfg<double, 128, 128, 16, MD_DEEP_OCC, 2, 4> {};
+template <> struct Deep<float> : TCfg<float, 128, 128, 32, MD_DEEP_OCC, 2, 4> {};
 // 256 x 256 tiles of 8 waves (64 x 128 each): half the operand bytes per
 // flop of a 128 x 128 tile, for the half computation precision, whose
 // one-plane LDS tiles fit (80 KB double-buffered).
@@ -125,6 +128,23 @@ struct Lay {
 // ---------------------------------------------------------------------------
 // Operand staging (cast-on-pack)
 // ---------------------------------------------------------------------------
+// A staged chunk, released component by component where it is used.  An LDS
+// write of the chunk as it is (double into an FP64 tile, float into an FP32
+// tile) or a conversion from a double takes two or four registers of the
+// loaded tuple together; across the k loop's back edge the compiler then
+// splits that tuple and copies it right after the global load, which waits
+// for the load at once.  And where parts of a chunk are never used (the
+// imaginary parts in cases 1a and 1b), their registers are taken as
+// temporaries while the load is still in flight, which waits for it too.
+// An empty statement that reads and rewrites all four components in place
+// (no instruction, no extra register) keeps every loaded register live until
+// here and gives the tuple only single-register uses, so the load stays in
+// flight through the MFMAs of a whole k-tile (checked on the generated code).
+__device__ __forceinline__ uint4 detach(uint4 h) {
+    asm("" : "+v"(h.x), "+v"(h.y), "+v"(h.z), "+v"(h.w));
+    return h;
+}
+
 enum Mode {
     M_PLAIN = 0,   // real operand
     M_REONLY = 1,  // complex operand of which only Re reaches C (1a: A, 1b: B)
@@ -197,6 +217,7 @@ struct Stage {
     bool half;                   // binary16 storage (generic path, single-width components)
     int64_t total_bytes;  // extent of the stored matrix
     bool mn_contig, conj;
+    uint32_t cmask;  // sign bit of the imaginary components when conjugating, else 0
     // Scaling by a complex alpha while staging (literal interpretation, real C):
     // only the complex operand of cases 1a, 1b and 2ab is ever scaled.  A
     // compile-time choice: a run-time branch here slows the unscaled kernels.
@@ -212,6 +233,7 @@ struct Stage {
         // A is stored along m for 'N'/'R', B along n for 'T'/'C'
         mn_contig = FAST ? MNC : (IS_A ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2));
         conj = tr >= 2;
+        cmask = (conj && W == 2) ? 0x80000000u : 0u;
         sre = (T)g.scale_re;
         sim = (T)g.scale_im;
         ld = IS_A ? g.lda : g.ldb;
@@ -406,10 +428,11 @@ struct Stage {
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;
+            const uint4 h = detach(raw[c]);
 #pragma unroll
             for (int q = 0; q < CW; q += 2) {
-                const T re = component(raw[c], q);
-                const T im0 = component(raw[c], q + 1);
+                const T re = component(h, q);
+                const T im0 = component(h, q + 1);
                 const T im = conj ? -im0 : im0;
                 const T pr = fma(sre, re, -(sim * im));
                 const T pi = fma(sre, im, sim * re);
@@ -432,18 +455,39 @@ struct Stage {
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
             const int col = col0 + c * col_step;
+            // conjugation flips the sign bit of every imaginary component in
+            // place (no select, no extra registers): the high word of the
+            // second double, the odd float words, or the upper binary16 half
+            // of every word
+            // (an operand of which only Re reaches C, stored as double,
+            // measured better without: its unused halves hold four registers
+            // per chunk and spill)
+            uint4 h = (MODE == M_REONLY && SDBL) ? raw[c] : detach(raw[c]);
+            if constexpr (W == 2) {
+                if constexpr (SDBL) {
+                    h.w ^= cmask;
+                } else if constexpr (SH) {
+                    h.x ^= cmask;
+                    h.y ^= cmask;
+                    h.z ^= cmask;
+                    h.w ^= cmask;
+                } else {
+                    h.y ^= cmask;
+                    h.w ^= cmask;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < CW; ++q) {
-                const T v = component(raw[c], q);
+                const T v = component(h, q);
                 const int e = pos * (CW / W) + q / W;
                 const int part = q % W;
                 if constexpr (FAST) {
-                    if constexpr (MNC) emit(out, e, col, part, v, conj);
-                    else emit(out, col, e, part, v, conj);
+                    if constexpr (MNC) emit(out, e, col, part, v, false);
+                    else emit(out, col, e, part, v, false);
                 } else {
                     const int mm = mn_contig ? e : col;
                     const int kk = mn_contig ? col : e;
-                    emit(out, mm, kk, part, v, conj);
+                    emit(out, mm, kk, part, v, false);
                 }
             }
         }
