@@ -212,8 +212,12 @@ int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k,
  * descriptor `index` (or MD_ERR_ALPHA_IMAG) and enqueues nothing.  The C
  * operands must be pairwise disjoint and must not overlap any A or B.  The
  * work table (one entry per product and per output tile, largest work first)
- * is uploaded into a stream-ordered device allocation that is released,
- * again in stream order, after the kernel; nothing else is allocated.  The
+ * is uploaded through page-locked staging into a device table that the
+ * library keeps per (device, stream): allocated on first use, grown on
+ * demand, kept until the process ends (the staging is reused once the
+ * previous upload from it has been read; calls on one stream may come from
+ * several host threads).  Products that take the plain kernels inside the
+ * call (see mdgemm_grouped_noalloc) follow mdgemm's allocation rules.  The
  * tile shape of each product comes from the tile-shape table below.
  */
 typedef struct {

@@ -35,13 +35,21 @@ SOURCES = [("mdgemm_grouped_kernel.hip", [], "grouped_kernel.o")] + [("mdgemm_ke
 ]
 
 
-def _newest_input(src):
-    """Modification time of the newest file an object of `src` depends on
-    (the source, every header under csrc/ and include/)."""
-    paths = [os.path.join(CSRC, src)]
-    for d in (CSRC, os.path.join(ROOT, "include")):
-        paths += [os.path.join(d, f) for f in os.listdir(d) if f.endswith(".h")]
-    return max(os.path.getmtime(p) for p in paths)
+def _newest_input(src, depfile):
+    """Modification time of the newest file an object of `src` depends on:
+    the files its compiler depfile lists, else the source and every header
+    under csrc/ and include/."""
+    paths = []
+    if os.path.exists(depfile):
+        text = open(depfile).read().replace("\\\n", " ")
+        for tok in text.split(":", 1)[-1].split():
+            if tok.startswith(ROOT) or not tok.startswith("/"):
+                paths.append(tok if tok.startswith("/") else os.path.join(ROOT, tok))
+    if not paths:
+        paths = [os.path.join(CSRC, src)]
+        for d in (CSRC, os.path.join(ROOT, "include")):
+            paths += [os.path.join(d, f) for f in os.listdir(d) if f.endswith(".h")]
+    return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
 
 
 def _compile(entry, extra=(), build_dir=BUILD, incremental=False):
@@ -50,14 +58,14 @@ def _compile(entry, extra=(), build_dir=BUILD, incremental=False):
     path = os.path.join(CSRC, src)
     obj = os.path.join(build_dir, objname)
     stamp = obj + ".flags"
+    dep = obj + ".d"
     key = " ".join(defs)
     if (incremental and os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key
-            and os.path.getmtime(obj) > _newest_input(src)):
+            and os.path.getmtime(obj) > _newest_input(src, dep)):
         return obj
-    if src.endswith(".hip"):
-        cmd = [HIPCC] + HIP_FLAGS + defs + ["-c", path, "-o", obj]
-    else:
-        cmd = [HIPCC] + CXX_FLAGS + defs + ["-c", path, "-o", obj]
+    flags = HIP_FLAGS if src.endswith(".hip") else CXX_FLAGS
+    # the host pass writes the depfile (every header either pass includes)
+    cmd = [HIPCC] + flags + defs + ["-MD", "-MF", dep, "-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), res.stderr))

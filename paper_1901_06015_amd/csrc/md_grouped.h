@@ -167,10 +167,11 @@ struct GStager {
             off[e] = (mn0 + i < o.MN) ? (int)((rel * W + comp) * esz) : (int)0x80000000;
         }
     }
-    // Load the E elements of k-tile t, converted to T (float -> double is
-    // exact, double -> float rounds to nearest even) and signed.
-    template <class T, bool DBL>
-    __device__ __forceinline__ void load(int t, T (&r)[E]) const {
+    // Issue the loads of the E elements of k-tile t: the raw words (the low
+    // word, and for double storage the high word, of each element).  They
+    // are converted only where they are stored (value), a k-tile later.
+    template <bool DBL>
+    __device__ __forceinline__ void issue(int t, uint32_t (&lo)[E], uint32_t (&hi)[E]) const {
         const int64_t b = tile0 + (int64_t)t * kbytes;
         const int64_t rem = total - b;
         const int nrec = rem > 0x7fffffffLL ? 0x7fffffff : (rem < 0 ? 0 : (int)rem);
@@ -181,17 +182,38 @@ struct GStager {
         for (int e = 0; e < E; ++e) {
             // along k the resource's end only bounds an m/n-contiguous operand
             const int o = (mnc || kp(e) < klim) ? off[e] : (int)0x80000000;
-            T v;
             if constexpr (DBL) {
-                const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, o, 0, 0);
-                v = (T)__builtin_bit_cast(double, ((uint64_t)x[1] << 32) | x[0]);
+                // two word loads rather than one pair, so that no register
+                // pair has to survive the k loop's back edge
+                lo[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0);
+                hi[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 4, 0, 0);
             } else {
-                v = (T)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0));
+                lo[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0);
             }
-            r[e] = ((negm >> e) & 1) ? -v : v;
         }
     }
+    // Element e of an issued k-tile, converted to T (float -> double is exact,
+    // double -> float rounds to nearest even) and signed.
+    template <class T, bool DBL>
+    __device__ __forceinline__ T value(int e, uint32_t lo, uint32_t hi) const {
+        T v;
+        if constexpr (DBL) v = (T)__builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+        else v = (T)__builtin_bit_cast(float, lo);
+        return ((negm >> e) & 1) ? -v : v;
+    }
 };
+
+// Raw words of a staged k-tile, pinned where they are converted: the loads
+// were issued a k-tile earlier, and this keeps the compiler from converting
+// (and so waiting for) them right after issuing them.
+template <int E, bool DBL>
+__device__ __forceinline__ void pin_raw(uint32_t (&lo)[E], uint32_t (&hi)[E]) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if constexpr (DBL) asm("" : "+v"(lo[e]), "+v"(hi[e]));
+        else asm("" : "+v"(lo[e]));
+    }
+}
 
 // Epilogue shared by the grouped tile routines: acc[a][b] item v is
 // C'(m = wm0 + 16a + (lane & 15), n = wn0 + 16b + acc_row(lane, v)).
@@ -269,28 +291,34 @@ __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, cha
     GStager<EB, BN, BK, LDW> sb;
     sa.init(oa, mn0a, tk, tid);
     sb.init(ob, mn0b, tk, tid);
-    T ra[EA], rb[EB];
-    auto load = [&](int t) {
-        sa.template load<T, AD>(t, ra);
-        sb.template load<T, BD>(t, rb);
+    uint32_t alo[EA], ahi[EA], blo[EB], bhi[EB];
+    auto issue = [&](int t) {
+        sa.template issue<AD>(t, alo, ahi);
+        sb.template issue<BD>(t, blo, bhi);
     };
     auto store = [&](int stage) {
+        pin_raw<EA, AD>(alo, ahi);
+        pin_raw<EB, BD>(blo, bhi);
         T *la = buf + stage * SH::STAGE, *lb = la + BK * LDW;
 #pragma unroll
-        for (int e = 0; e < EA; ++e) la[sa.slot(e)] = ra[e];
+        for (int e = 0; e < EA; ++e) la[sa.slot(e)] = sa.template value<T, AD>(e, alo[e], ahi[e]);
 #pragma unroll
-        for (int e = 0; e < EB; ++e) lb[sb.slot(e)] = rb[e];
+        for (int e = 0; e < EB; ++e) lb[sb.slot(e)] = sb.template value<T, BD>(e, blo[e], bhi[e]);
     };
 
-    // Two LDS stages: tile t+1 is loaded during the MFMAs of tile t and
-    // written to the other stage (last read before the previous barrier), so
-    // one barrier per k-tile suffices.
-    load(0);
+    // Two LDS stages and one k-tile of loads in flight: iteration t first
+    // writes the raw words of tile t+1 (issued during iteration t-1) to the
+    // free stage (last read before the previous barrier), then issues the
+    // loads of tile t+2, then multiplies tile t, so every load has a whole
+    // k-tile of MFMAs to arrive; one barrier per k-tile.
+    issue(0);
     store(0);
+    if (nk > 1) issue(1);
     __syncthreads();
     for (int t = 0; t < nk; ++t) {
         const T *la = buf + (t & 1) * SH::STAGE, *lb = la + BK * LDW;
-        if (t + 1 < nk) load(t + 1);
+        if (t + 1 < nk) store((t + 1) & 1);
+        if (t + 2 < nk) issue(t + 2);
 #pragma unroll
         for (int s = 0; s < BK / 4; ++s) {
             const int kr = s * 4 + (lane >> 4);
@@ -304,7 +332,6 @@ __device__ __forceinline__ void grouped_tile(const GDesc &d, int tm, int tn, cha
 #pragma unroll
                 for (int b = 0; b < WB; ++b) acc[a][b] = mfma16(fb[b], fa[a], acc[a][b]);
         }
-        if (t + 1 < nk) store((t + 1) & 1);
         __syncthreads();
     }
     grouped_epilogue<T, acc_t, WB>(g, mdbl, ndbl, ccplx, (int64_t)tm * tmn_a, (int64_t)tn * tmn_b, wm0, wn0,
@@ -340,21 +367,25 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
     GStager<EB, BN, BK, LDW> sb;
     sa.init(oa, mn0a, tk, tid);
     sb.init(ob, mn0b, tk, tid);
-    float ra[EA], rb[EB];
-    auto load = [&](int t) {
-        sa.template load<float, AD>(t, ra);
-        sb.template load<float, BD>(t, rb);
+    uint32_t alo[EA], ahi[EA], blo[EB], bhi[EB];
+    auto issue = [&](int t) {
+        sa.template issue<AD>(t, alo, ahi);
+        sb.template issue<BD>(t, blo, bhi);
     };
     auto split = [](float v, __bf16 &h, __bf16 &l) {
         h = (__bf16)v;
         l = (__bf16)(v - (float)h);
     };
     auto store = [&](int stage) {
+        pin_raw<EA, AD>(alo, ahi);
+        pin_raw<EB, BD>(blo, bhi);
         __bf16 *ah = buf + stage * STAGE, *al = ah + PLANE, *bh = al + PLANE, *bl = bh + PLANE;
 #pragma unroll
-        for (int e = 0; e < EA; ++e) split(ra[e], ah[sa.slot(e)], al[sa.slot(e)]);
+        for (int e = 0; e < EA; ++e)
+            split(sa.template value<float, AD>(e, alo[e], ahi[e]), ah[sa.slot(e)], al[sa.slot(e)]);
 #pragma unroll
-        for (int e = 0; e < EB; ++e) split(rb[e], bh[sb.slot(e)], bl[sb.slot(e)]);
+        for (int e = 0; e < EB; ++e)
+            split(sb.template value<float, BD>(e, blo[e], bhi[e]), bh[sb.slot(e)], bl[sb.slot(e)]);
     };
     static_assert(LDW % 4 == 0, "transposing reads need 8-byte aligned rows");
     // k = 8g .. 8g+7 of column w0 + 16 i + (lane & 15) in two transposing
@@ -366,12 +397,16 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
         return bf16x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
     };
 
-    load(0);
+    // the k loop of grouped_tile: raw words of tile t+1 stored first, loads
+    // of tile t+2 issued, then the MFMAs of tile t
+    issue(0);
     store(0);
+    if (nk > 1) issue(1);
     __syncthreads();
     for (int t = 0; t < nk; ++t) {
         const __bf16 *ah = buf + (t & 1) * STAGE, *al = ah + PLANE, *bh = al + PLANE, *bl = bh + PLANE;
-        if (t + 1 < nk) load(t + 1);
+        if (t + 1 < nk) store((t + 1) & 1);
+        if (t + 2 < nk) issue(t + 2);
         bf16x8 fah[WB], fal[WB], fbh[WB], fbl[WB];
 #pragma unroll
         for (int i = 0; i < WB; ++i) {
@@ -388,7 +423,6 @@ __device__ __forceinline__ void grouped_tile_bf16x3(const GDesc &d, int tm, int 
                 acc[a][b] = mfma_bf16(fbh[b], fal[a], acc[a][b]);
                 acc[a][b] = mfma_bf16(fbh[b], fah[a], acc[a][b]);
             }
-        if (t + 1 < nk) store((t + 1) & 1);
         __syncthreads();
     }
     grouped_epilogue<float, v4f, WB>(g, mdbl, ndbl, ccplx, (int64_t)tm * tmn_a, (int64_t)tn * tmn_b, wm0, wn0,

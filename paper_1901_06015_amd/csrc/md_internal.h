@@ -75,6 +75,7 @@ struct GemmArgs {
     int a_scale, b_scale;       // stage A (B) as (scale_re + i scale_im) times itself: a complex
     double scale_re, scale_im;  // alpha under the literal interpretation with C real
     int tiles_m, tiles_n;     // workgroup tiles of the real product
+    int small;                // runs on md_small_kernel: 32 x 32 real-product tiles (md_small.h)
     int splits;               // > 1: k split over this many workgroups per tile (plain kernels)
     void *part;               // their partial products: splits x n x m pairs (re, im) of the
                               // computation type, summed and finished by md_split_reduce
@@ -114,6 +115,14 @@ constexpr int tile_kind(int prec, int cs, bool fast) {
          : (MD_WIDE & (prec == PREC_D ? 16 : 32)) ? 3 : 0 * cs;
 }
 
+// Products with few output tiles run on md_small_kernel (md_small.h): at
+// most SMALL_MAX_TILES tiles of the tiled kernel and an inner dimension of the
+// real product of at most SMALL_MAX_K.  MDGEMM_SMALL=0 in the environment
+// turns it off (read on every call).
+constexpr int SMALL_TILE = 32;
+constexpr int SMALL_MAX_TILES = 16;
+constexpr int64_t SMALL_MAX_K = 2048;
+
 // Everything mdgemm decides before touching the device (mdgemm_api.cpp).
 struct Decision {
     int status = MD_OK;
@@ -133,6 +142,7 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
 // may_split false: never split k, so nothing is allocated (the split-k
 // workspace is the plain path's only allocation).
 int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out, bool may_split = true);
+int launch_small(int prec, int cs, const GemmArgs &a, void *stream);
 int launch_scale(const GemmArgs &a, void *stream);
 void tile_shape(int prec, int cs, bool fast, int *bm, int *bn, int *bk);
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len);

@@ -2,6 +2,7 @@
 // classification (Figure "mixeddom"), the computation-precision and scalar
 // policies (Sections 5.1 and 7), quick returns, and dispatch to the kernels.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "md_internal.h"
@@ -204,7 +205,18 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
     const Lowering L = lower_case(d.cs);
     int bm, bn, bk;
     tile_shape(d.prec, d.cs, g.a_vec && g.b_vec, &bm, &bn, &bk);
-    const int64_t tmn_a = bm / (L.mdbl ? 2 : 1), tmn_b = bn / (L.ndbl ? 2 : 1);
+    int64_t tmn_a = bm / (L.mdbl ? 2 : 1), tmn_b = bn / (L.ndbl ? 2 : 1);
+    // few tiles: the small kernel (single and double precision, BLAS storage,
+    // no binary16 operand, no operand staged with alpha)
+    const int64_t tiles = ((m + tmn_a - 1) / tmn_a) * ((n + tmn_b - 1) / tmn_b);
+    const char *sm = getenv("MDGEMM_SMALL");
+    if ((d.prec == PREC_S || d.prec == PREC_D) && !(sm && sm[0] == '0') && tiles <= SMALL_MAX_TILES &&
+        k * (L.kdbl ? 2 : 1) <= SMALL_MAX_K && rsa == 1 && rsb == 1 && plain_c && !g.a_half && !g.b_half &&
+        !a_scale && !b_scale) {
+        g.small = 1;
+        tmn_a = SMALL_TILE / (L.mdbl ? 2 : 1);
+        tmn_b = SMALL_TILE / (L.ndbl ? 2 : 1);
+    }
     g.tiles_m = (int)((m + tmn_a - 1) / tmn_a);
     g.tiles_n = (int)((n + tmn_b - 1) / tmn_b);
     return d;
@@ -312,6 +324,7 @@ int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
         out->flops = (double)L.flop_factor * (double)m * (double)n * (double)k;
         int bm, bn, bk;
         tile_shape(d.prec, d.cs, d.g.a_vec && d.g.b_vec, &bm, &bn, &bk);
+        if (d.g.small) bm = bn = SMALL_TILE, bk = 4;
         out->tile_m = bm; out->tile_n = bn; out->tile_k = bk;
         out->workgroups = (int64_t)d.g.tiles_m * d.g.tiles_n;
         kernel_name(d.prec, d.cs, d.g, out->kernel, (int)sizeof(out->kernel));

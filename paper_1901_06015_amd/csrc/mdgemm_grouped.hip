@@ -5,7 +5,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "md_grouped.h"
@@ -43,6 +45,22 @@ int choose_cfg(int prec, int cs, int64_t m_real, int64_t n_real) {
 }
 
 int g_num_cu = 0;
+
+// Upload staging of mdgemm_grouped, one per (device, stream): page-locked host
+// memory and a device table, grown on demand and kept until the process ends.
+// An event marks when the last upload from the host buffer has been read, so
+// the next call on the stream waits for it (usually not at all) before
+// writing the buffer again; the device table is only rewritten by a later
+// upload on the same stream, after the kernel that read it.
+struct UploadCache {
+    char *host = nullptr;
+    char *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t read = nullptr;
+    bool pending = false;
+};
+std::mutex g_up_mu;
+std::map<std::pair<int, hipStream_t>, UploadCache> g_up;
 
 // The work table of mdgemm_grouped_noalloc: a fixed array that every GPU the
 // library runs on holds until the process ends.  In host code the array's
@@ -94,10 +112,11 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
     if (count == 0) return MD_OK;
     if (!descs) return -2;
     std::vector<GDesc> gd;
-    std::vector<GTile> tiles;
-    std::vector<double> work;
+    std::vector<double> work;    // per product in gd: estimated cost of one of its tiles
     std::vector<int64_t> alone;  // products run by the plain kernels instead
+    int64_t ntiles64 = 0;
     gd.reserve(count);
+    work.reserve(count);
     for (int64_t i = 0; i < count; ++i) {
         const md_gemm_desc &x = descs[i];
         Decision d = decide(x.transa, x.transb, x.m, x.n, x.k, x.alpha, x.A, x.dta, x.lda, x.B, x.dtb, x.ldb,
@@ -145,13 +164,11 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         const double kr = (double)x.k * (L.kdbl ? 2 : 1);
         const double w = e.kind == 1 ? (double)edge * edge
                                      : (double)edge * edge * kr * (d.prec == PREC_D ? 2.0 : (d.prec == PREC_S ? 1.0 : 0.5));
-        for (int tm = 0; tm < e.tiles_m; ++tm)
-            for (int tn = 0; tn < e.tiles_n; ++tn) {
-                tiles.push_back(GTile{di, tm, tn, 0});
-                work.push_back(w);
-            }
+        work.push_back(w);
+        ntiles64 += (int64_t)e.tiles_m * e.tiles_n;
+        (void)di;
     }
-    if (tiles.size() > 0x7fffffffu) return MD_ERR_UNSUPPORTED;
+    if (ntiles64 > 0x7fffffffLL) return MD_ERR_UNSUPPORTED;
     auto run_alone = [&]() {
         for (int64_t i : alone) {
             const int rc = gemm_enqueue(descs[i], c_in ? c_in[i] : nullptr, stream, !noalloc);
@@ -159,21 +176,26 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         }
         return (int)MD_OK;
     };
-    if (tiles.empty()) return run_alone();
+    if (ntiles64 == 0) return run_alone();
     // Largest work first (LPT order) so the tail of the queue is short tiles.
-    std::vector<int> order(tiles.size());
+    // All tiles of a product cost the same, so ordering the products (stably)
+    // and listing each product's tiles in turn gives the tile order.
+    std::vector<int> order(gd.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
 
+    const size_t ntiles_all = (size_t)ntiles64;
     const size_t hdr_bytes = 256;
     const size_t desc_bytes = gd.size() * sizeof(GDesc);
-    const size_t tile_bytes = tiles.size() * sizeof(GTile);
+    const size_t tile_bytes = ntiles_all * sizeof(GTile);
     const size_t total = hdr_bytes + desc_bytes + tile_bytes;
     // the size is checked before any device call
     if (noalloc && total > MD_GROUPED_NOALLOC_BYTES) return MD_ERR_SCRATCH;
     hipStream_t s = (hipStream_t)stream;
     std::vector<char> tmp;
     char *host = nullptr, *dev = nullptr;
+    std::unique_lock<std::mutex> up_lock(g_up_mu, std::defer_lock);
+    UploadCache *up = nullptr;
     if (noalloc) {
         // the fixed array of this device; the host copy is consumed by the
         // upload before hipMemcpyAsync returns
@@ -201,24 +223,60 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         host = ws->host;
         dev = ws->dev;
     } else {
-        tmp.resize(total);
-        host = tmp.data();
-        if (hipMallocAsync((void **)&dev, total, s) != hipSuccess) return MD_ERR_HIP;
+        int dv = 0;
+        if (hipGetDevice(&dv) != hipSuccess) return MD_ERR_HIP;
+        // held until the kernel is enqueued: host threads sharing a stream
+        // take turns with the staging
+        up_lock.lock();
+        up = &g_up[std::make_pair(dv, s)];
+        if (up->pending) {
+            if (hipEventSynchronize(up->read) != hipSuccess) return MD_ERR_HIP;
+            up->pending = false;
+        }
+        if (up->cap < total) {
+            if (up->host) (void)hipHostFree(up->host);
+            if (up->dev) (void)hipFreeAsync(up->dev, s);
+            up->host = nullptr;
+            up->dev = nullptr;
+            up->cap = 0;
+            const size_t cap = std::max<size_t>(total + total / 2, 1 << 20);
+            if (hipHostMalloc((void **)&up->host, cap, hipHostMallocDefault) != hipSuccess) {
+                up->host = nullptr;
+                return MD_ERR_HIP;
+            }
+            if (hipMallocAsync((void **)&up->dev, cap, s) != hipSuccess) {
+                (void)hipHostFree(up->host);
+                up->host = nullptr;
+                up->dev = nullptr;
+                return MD_ERR_HIP;
+            }
+            up->cap = cap;
+        }
+        if (!up->read && hipEventCreateWithFlags(&up->read, hipEventDisableTiming) != hipSuccess) {
+            up->read = nullptr;
+            return MD_ERR_HIP;
+        }
+        host = up->host;
+        dev = up->dev;
     }
     memset(host, 0, hdr_bytes);  // the tile-queue counter starts at zero
     memcpy(host + hdr_bytes, gd.data(), desc_bytes);
     GTile *ht = (GTile *)(host + hdr_bytes + desc_bytes);
-    for (size_t i = 0; i < order.size(); ++i) ht[i] = tiles[order[i]];
-    if (hipMemcpyAsync(dev, host, total, hipMemcpyHostToDevice, s) != hipSuccess) {
-        if (!ws && !noalloc) (void)hipFreeAsync(dev, s);
-        return MD_ERR_HIP;
+    size_t nt = 0;
+    for (int di : order)
+        for (int tm = 0; tm < gd[di].tiles_m; ++tm)
+            for (int tn = 0; tn < gd[di].tiles_n; ++tn) ht[nt++] = GTile{di, tm, tn, 0};
+    if (hipMemcpyAsync(dev, host, total, hipMemcpyHostToDevice, s) != hipSuccess) return MD_ERR_HIP;
+    if (up) {
+        if (hipEventRecord(up->read, s) != hipSuccess) return MD_ERR_HIP;
+        up->pending = true;
     }
-    const int ntiles = (int)tiles.size();
+    const int ntiles = (int)ntiles_all;
     const int grid = std::min(ntiles, num_cu() * GROUPED_OCC);
     launch_grouped_kernel(grid, s, (const GDesc *)(dev + hdr_bytes), (const GTile *)(dev + hdr_bytes + desc_bytes),
                           ntiles, (int *)dev);
     const hipError_t le = hipGetLastError();
-    if (!ws && !noalloc) (void)hipFreeAsync(dev, s);
+    if (up_lock.owns_lock()) up_lock.unlock();
     if (le != hipSuccess) return MD_ERR_HIP;
     return run_alone();
 }

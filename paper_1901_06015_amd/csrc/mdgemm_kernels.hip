@@ -5,6 +5,7 @@
 // that the variants (4 computation precisions x 8 cases x 4 storage precisions
 // of A and B x 5 load paths: the fast path for each of the 4 operand
 // orientations and the generic path) build in parallel.
+#include "md_small.h"
 #include "md_tile.h"
 #include "md_tile_bf16.h"
 
@@ -116,9 +117,25 @@ static void launch_c(const GemmArgs &a, hipStream_t s, unsigned nwg) {
 
 #define MD_PART_NAME2(t, c) launch_part_##t##_##c
 #define MD_PART_NAME(t, c) MD_PART_NAME2(t, c)
+#define MD_SMALL_NAME2(t, c) launch_small_##t##_##c
+#define MD_SMALL_NAME(t, c) MD_SMALL_NAME2(t, c)
 
 void MD_PART_NAME(MD_KT, MD_KCASE)(const GemmArgs &a, hipStream_t s, unsigned nwg) {
     launch_c<MD_KCASE>(a, s, nwg);
 }
+
+#if MD_KT == 0 || MD_KT == 1
+// The small kernel of this precision and case, for each storage precision of
+// A and B.
+void MD_SMALL_NAME(MD_KT, MD_KCASE)(const GemmArgs &a, hipStream_t s, unsigned nwg) {
+    if (a.a_dbl) {
+        if (a.b_dbl) hipLaunchKernelGGL((md_small_kernel<KT, MD_KCASE, true, true>), dim3(nwg), dim3(SM_NT), 0, s, a);
+        else hipLaunchKernelGGL((md_small_kernel<KT, MD_KCASE, true, false>), dim3(nwg), dim3(SM_NT), 0, s, a);
+    } else {
+        if (a.b_dbl) hipLaunchKernelGGL((md_small_kernel<KT, MD_KCASE, false, true>), dim3(nwg), dim3(SM_NT), 0, s, a);
+        else hipLaunchKernelGGL((md_small_kernel<KT, MD_KCASE, false, false>), dim3(nwg), dim3(SM_NT), 0, s, a);
+    }
+}
+#endif
 
 }  // namespace md

@@ -29,6 +29,18 @@ MD_DECL_PARTS(1)
 MD_DECL_PARTS(2)
 MD_DECL_PARTS(3)
 
+#define MD_DECL_SMALL(t)                                                       \
+    void launch_small_##t##_0(const GemmArgs &, hipStream_t, unsigned);        \
+    void launch_small_##t##_1(const GemmArgs &, hipStream_t, unsigned);        \
+    void launch_small_##t##_2(const GemmArgs &, hipStream_t, unsigned);        \
+    void launch_small_##t##_3(const GemmArgs &, hipStream_t, unsigned);        \
+    void launch_small_##t##_4(const GemmArgs &, hipStream_t, unsigned);        \
+    void launch_small_##t##_5(const GemmArgs &, hipStream_t, unsigned);        \
+    void launch_small_##t##_6(const GemmArgs &, hipStream_t, unsigned);        \
+    void launch_small_##t##_7(const GemmArgs &, hipStream_t, unsigned);
+MD_DECL_SMALL(0)
+MD_DECL_SMALL(1)
+
 typedef void (*part_fn)(const GemmArgs &, hipStream_t, unsigned);
 // [PREC_S, PREC_D, PREC_BF16X3, PREC_H][case]
 static const part_fn kParts[4][8] = {
@@ -40,6 +52,12 @@ static const part_fn kParts[4][8] = {
      launch_part_2_4, launch_part_2_5, launch_part_2_6, launch_part_2_7},
     {launch_part_3_0, launch_part_3_1, launch_part_3_2, launch_part_3_3,
      launch_part_3_4, launch_part_3_5, launch_part_3_6, launch_part_3_7}};
+// the small kernel, [PREC_S, PREC_D][case]
+static const part_fn kSmall[2][8] = {
+    {launch_small_0_0, launch_small_0_1, launch_small_0_2, launch_small_0_3,
+     launch_small_0_4, launch_small_0_5, launch_small_0_6, launch_small_0_7},
+    {launch_small_1_0, launch_small_1_1, launch_small_1_2, launch_small_1_3,
+     launch_small_1_4, launch_small_1_5, launch_small_1_6, launch_small_1_7}};
 
 // C := beta*C (alpha == 0 or k == 0).  beta == 0 writes zeros without reading C.
 __global__ __launch_bounds__(256) void md_scale_kernel(GemmArgs g) {
@@ -192,6 +210,7 @@ int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg,
     if (wg) *wg = n;
     if (n <= 0) return 0;
     if (prec < PREC_S || prec > PREC_H || cs < 0 || cs > 7) return MD_ERR_UNSUPPORTED;
+    if (a0.small) return launch_small(prec, cs, a0, stream);
     hipStream_t s = (hipStream_t)stream;
     GemmArgs a = a0;
     a.splits = may_split ? split_count(prec, cs, a0, n) : 1;
@@ -207,6 +226,15 @@ int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg,
     } else {
         enqueue_product(prec, cs, a, s, n);
     }
+    return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
+}
+
+// One workgroup per 32 x 32 tile of the real product (md_small.h).
+int launch_small(int prec, int cs, const GemmArgs &a, void *stream) {
+    const int64_t n = (int64_t)a.tiles_m * a.tiles_n;
+    if (n <= 0) return 0;
+    if (prec != PREC_S && prec != PREC_D) return MD_ERR_UNSUPPORTED;
+    kSmall[prec][cs](a, (hipStream_t)stream, (unsigned)n);
     return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
 }
 
@@ -233,8 +261,9 @@ void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len) {
     snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c_%s",
              prec == PREC_D ? "f64" : prec == PREC_S ? "f32" : prec == PREC_H ? "f16" : "bf16x3",
              (cs >= 0 && cs < 8) ? cases[cs] : "?",
-             (a.a_vec && a.b_vec) ? ((a.a_ragged || a.b_ragged) ? "ragged" : "fast") : "generic",
-             a.a_dbl ? 'd' : (a.a_half ? 'h' : 's'), a.b_dbl ? 'd' : (a.b_half ? 'h' : 's'), tiles[kind]);
+             a.small ? "small" : (a.a_vec && a.b_vec) ? ((a.a_ragged || a.b_ragged) ? "ragged" : "fast") : "generic",
+             a.a_dbl ? 'd' : (a.a_half ? 'h' : 's'), a.b_dbl ? 'd' : (a.b_half ? 'h' : 's'),
+             a.small ? "t32x32w8" : tiles[kind]);
 }
 
 }  // namespace md

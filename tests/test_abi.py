@@ -14,6 +14,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TAGS = ("s", "d", "c", "z")
 
 
+@pytest.fixture(autouse=True)
+def _tiled_planner(monkeypatch):
+    """The planner tests below are about the tiled kernels: products with few
+    tiles would otherwise take the small kernel (test_small_kernel_choice)."""
+    monkeypatch.setenv("MDGEMM_SMALL", "0")
+
+
 def declared_functions():
     names = set()
     for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
@@ -292,3 +299,26 @@ def test_grouped_noalloc_rejects_an_oversized_table():
     st = _lib.mdgemm_grouped_noalloc(descs, None)
     assert st == _lib.MD_ERR_SCRATCH, st
     assert "scratch" in _lib.strerror(st)
+
+
+def test_small_kernel_choice(monkeypatch):
+    """The planner sends products with few tiles and a short inner dimension
+    to the small kernel (32 x 32 tiles of the real product, eight waves
+    sharing k) and the others to the tiled kernels; MDGEMM_SMALL=0 turns it
+    off."""
+    monkeypatch.delenv("MDGEMM_SMALL")
+
+    def plan(m, n, k, ta="c", tb="d", tc="z", comp="d"):
+        st, p = _lib.mdgemm_plan("N", "N", m, n, k, 1.0, 0x1000, ta, m, 0x1000, tb, k, 1.0, 0x1000, tc, m, comp)
+        assert st == 0
+        return p
+    p = plan(256, 256, 256)  # the single-product configuration: case 2ac, real product 512 x 256
+    assert "small" in p["kernel"] and p["workgroups"] == 16 * 8 and (p["tile_m"], p["tile_n"]) == (32, 32), p
+    assert "small" not in plan(4096, 4096, 4096)["kernel"]
+    assert "small" not in plan(256, 256, 4096)["kernel"]          # k' above the small kernel's limit
+    assert "small" in plan(64, 64, 1024, "z", "z", "z")["kernel"]   # case 3: k' = 2048
+    assert "small" not in plan(64, 64, 1025, "z", "z", "z")["kernel"]
+    assert "small" not in plan(64, 64, 64, "h", "h", "h", "h")["kernel"]  # binary16 operands
+    assert "small" not in plan(64, 64, 64, comp="bf16x3")["kernel"]
+    monkeypatch.setenv("MDGEMM_SMALL", "0")
+    assert "small" not in plan(256, 256, 256)["kernel"]

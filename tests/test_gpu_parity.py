@@ -31,6 +31,26 @@ def _device():
     yield
 
 
+# Products with few tiles run on the small kernel by default; "tiled" runs the
+# same tests with MDGEMM_SMALL=0, on the tiled kernels (fast, ragged and
+# component-wise loads, split k).
+PATHS = ["small", "tiled"]
+
+
+@pytest.fixture
+def path(request, monkeypatch):
+    if request.param == "tiled":
+        monkeypatch.setenv("MDGEMM_SMALL", "0")
+    else:
+        monkeypatch.delenv("MDGEMM_SMALL", raising=False)
+    return request.param
+
+
+@pytest.fixture
+def tiled(monkeypatch):
+    monkeypatch.setenv("MDGEMM_SMALL", "0")
+
+
 def one(tc, ta, tb, m, n, k, comp, transa="N", transb="N", alpha=1.5, beta=-0.5, **kw):
     say("mdgemm %s%s%s comp=%s %s%s m=%d n=%d k=%d %r" % (tc, ta, tb, comp, transa, transb, m, n, k, kw))
     st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp=comp, transa=transa, transb=transb,
@@ -44,7 +64,8 @@ def one(tc, ta, tb, m, n, k, comp, transa="N", transb="N", alpha=1.5, beta=-0.5,
 
 @pytest.mark.parametrize("comp", ["s", "d"])
 @pytest.mark.parametrize("tc", TAGS)
-def test_all_storage_combinations(tc, comp):
+@pytest.mark.parametrize("path", PATHS, indirect=True)
+def test_all_storage_combinations(tc, comp, path):
     """All 16 (A, B) storage pairs for this C and computation precision, at a
     size that spans several workgroup tiles and k tiles with ragged edges."""
     for ta, tb in itertools.product(TAGS, TAGS):
@@ -52,7 +73,8 @@ def test_all_storage_combinations(tc, comp):
 
 
 @pytest.mark.parametrize("transa,transb", list(itertools.product("NTCR", "NTCR")))
-def test_transpose_variants(transa, transb):
+@pytest.mark.parametrize("path", PATHS, indirect=True)
+def test_transpose_variants(transa, transb, path):
     """The nine op(A), op(B) combinations of Section 1 plus conjugation
     without transposition (R, Section 3), on a combination of every domain
     case."""
@@ -63,7 +85,8 @@ def test_transpose_variants(transa, transb):
 
 
 @pytest.mark.parametrize("comp", ["s", "d"])
-def test_exact_inputs_bitwise(comp):
+@pytest.mark.parametrize("path", PATHS, indirect=True)
+def test_exact_inputs_bitwise(comp, path):
     """Integer entries in [-4, 4], alpha = 1.5, beta = -0.5: every rounding in
     either precision is exact, so the GPU must equal the oracle bit for bit,
     whatever its summation order."""
@@ -79,7 +102,8 @@ def test_exact_inputs_bitwise(comp):
 
 
 @pytest.mark.parametrize("cab", ["zcd", "ccs", "zzz", "sdd", "dcz", "csz", "zss", "szc"])
-def test_edge_sizes(cab):
+@pytest.mark.parametrize("path", PATHS, indirect=True)
+def test_edge_sizes(cab, path):
     """Tile edges and degenerate sizes (0 and 1 included), both precisions."""
     sizes = (0, 1, 2, 3, 5, 17, 33, 65, 129)
     rng = np.random.Generator(np.random.PCG64(5))
@@ -89,7 +113,8 @@ def test_edge_sizes(cab):
             one(cab[0], cab[1], cab[2], m, n, k, comp)
 
 
-def test_unaligned_leading_dimensions():
+@pytest.mark.parametrize("path", PATHS, indirect=True)
+def test_unaligned_leading_dimensions(path):
     """Odd leading dimensions defeat 16-byte loads: the component-wise load
     path must give the same result; the padding rows are never written."""
     for cab, comp in (("zcd", "d"), ("sds", "s"), ("czz", "s"), ("dzc", "d")):
@@ -460,7 +485,7 @@ def test_half_torch_tensors():
 
 
 @pytest.mark.parametrize("comp", ["s", "d"])
-def test_split_k_small_tiles(comp):
+def test_split_k_small_tiles(comp, tiled):
     """Products with few tiles and a deep k split k over several workgroups
     (partials in the computation type, summed in split order, one epilogue):
     every domain case, fast and component-wise loads, ragged k, a half C."""
@@ -475,7 +500,7 @@ def test_split_k_small_tiles(comp):
         one(tc, ta, tb, m, n, k, comp, "T" if i % 4 == 1 else "N", "N", pad_a=0 if i % 4 == 1 else pad)
 
 
-def test_split_k_exact_and_strided():
+def test_split_k_exact_and_strided(tiled):
     """Split k on integer inputs gives the oracle bit for bit; a general-stride
     and a row-major C through the split path stay within the bound."""
     for tc, ta, tb, comp in (("z", "c", "d", "d"), ("s", "s", "s", "s"), ("c", "z", "z", "s"), ("d", "d", "c", "d")):
@@ -515,3 +540,26 @@ def test_large_ld_operand_stored_along_k(comp):
     assert ("generic" in p["kernel"]) == (comp == "h"), p["kernel"]
     say("large ld along k:", p["kernel"])
     one("s", "s", "z", m, n, k, comp, pad_b=ldb - k)
+
+
+@pytest.mark.parametrize("comp", ["s", "d"])
+def test_small_kernel_k_edges(comp):
+    """The small kernel at inner dimensions around its wave split and step
+    size (k' = 1 .. 9, odd, at its limit) and tile edges, every case."""
+    combos = ["ddd", "sdc", "dzs", "scz", "csd", "zdz", "czs", "zcz"]
+    for i, cab in enumerate(combos):
+        for k in (1, 2, 3, 5, 9, 31, 33):
+            one(cab[0], cab[1], cab[2], 33 + i, 47 - i, k, comp, "NTCR"[i % 4], "NTCR"[(i + k) % 4])
+        kmax = 2048 // (2 if cab[1] in "cz" and cab[2] in "cz" else 1)
+        one(cab[0], cab[1], cab[2], 65, 31, kmax, comp)
+
+
+def test_small_kernel_exact_inputs_bitwise():
+    """Integer inputs on the small kernel: bitwise equal to the oracle."""
+    for tc, ta, tb in itertools.product(TAGS, TAGS, TAGS):
+        for comp in ("s", "d"):
+            st, Cout, ops = gu.run(tc, ta, tb, 70, 66, 300, comp=comp, dist="int", seed=21)
+            assert st == 0
+            ref, _ = gu.reference(tc, ta, tb, 70, 66, 300, ops)
+            got = np.asarray(Cout[:70, :66], dtype=np.complex128)
+            assert np.array_equal(got, ref), "small exact %s%s%s/%s" % (tc, ta, tb, comp)
