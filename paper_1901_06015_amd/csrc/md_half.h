@@ -10,14 +10,13 @@ namespace md {
 // this value to binary16 gives the nearest-even binary16 value of x itself:
 // one rounding, not two.
 __device__ __forceinline__ float float_rto(double x) {
-    float f = (float)x;
-    if ((double)f != x) {
-        uint32_t u = __float_as_uint(f);
-        if (fabs((double)f) > fabs(x)) u -= 1;  // rounded away from zero: step back
-        u |= 1u;
-        f = __uint_as_float(u);
-    }
-    return f;
+    // branch-free (selects): inside the k loop a branch here would split the
+    // loop and make the staging wait for its loads at once
+    const float f = (float)x;
+    const bool inexact = (double)f != x;
+    const bool away = fabs((double)f) > fabs(x);  // rounded away from zero: step back
+    const uint32_t u = __float_as_uint(f) - (uint32_t)(inexact & away);
+    return __uint_as_float(u | (uint32_t)inexact);
 }
 
 // Nearest-even binary16 value of a double, with a single rounding.

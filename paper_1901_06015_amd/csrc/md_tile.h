@@ -90,9 +90,24 @@ template <> struct WideM<float> : TCfg<float, 256, 128, 32, 2, 4, 2> {};
 #ifndef MD_DEEP_OCC
 #define MD_DEEP_OCC 4
 #endif
+// Build knobs of the FP32 form (measured against the defaults on the sweep):
+// MD_F32_BK its k depth, MD_F32_OCC its waves per SIMD, MD_F32_WGM x
+// MD_F32_WGN its wave grid.
+#ifndef MD_F32_BK
+#define MD_F32_BK 32
+#endif
+#ifndef MD_F32_OCC
+#define MD_F32_OCC MD_DEEP_OCC
+#endif
+#ifndef MD_F32_WGM
+#define MD_F32_WGM 2
+#endif
+#ifndef MD_F32_WGN
+#define MD_F32_WGN 4
+#endif
 template <class T> struct Deep;
 template <> struct Deep<double> : TCfg<double, 128, 128, 16, MD_DEEP_OCC, 2, 4> {};
-template <> struct Deep<float> : TCfg<float, 128, 128, 32, MD_DEEP_OCC, 2, 4> {};
+template <> struct Deep<float> : TCfg<float, 128, 128, MD_F32_BK, MD_F32_OCC, MD_F32_WGM, MD_F32_WGN> {};
 // 256 x 256 tiles of 8 waves (64 x 128 each): half the operand bytes per
 // flop of a 128 x 128 tile, for the half computation precision, whose
 // one-plane LDS tiles fit (80 KB double-buffered).
@@ -406,6 +421,7 @@ struct Stage {
 
     // Writes one element of the real product's tile into an LDS buffer of T.
     struct PlainOut {
+        static constexpr bool NARROW = false;  // values go to LDS in T
         T *lds;
         __device__ __forceinline__ void put(int kk, int mm, T v) const { lds[L::at(kk, mm)] = v; }
     };
@@ -462,7 +478,9 @@ struct Stage {
             // (an operand of which only Re reaches C, stored as double,
             // measured better without: its unused halves hold four registers
             // per chunk and spill)
-            uint4 h = (MODE == M_REONLY && SDBL) ? raw[c] : detach(raw[c]);
+            // (not needed where every value is converted to 16 bits on its
+            // way to LDS: the BF16x3 and half outputs; there it costs a copy)
+            uint4 h = ((MODE == M_REONLY && SDBL) || Out::NARROW) ? raw[c] : detach(raw[c]);
             if constexpr (W == 2) {
                 if constexpr (SDBL) {
                     h.w ^= cmask;
@@ -804,7 +822,10 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
     //                                   col n = wn0 + 16b + acc_row(lane, v)).
     // A split workgroup stores its partial (re, im) instead.  Split and
     // binary16-C stores are decided once per workgroup, so the common case
-    // keeps the plain epilogue's code.
+    // keeps the plain epilogue's code.  Where a thread holds many
+    // accumulators the general update is too large to inline at each: its
+    // loop over row blocks stays rolled and picks the accumulator with
+    // selects (an indexed access would put the accumulators in scratch).
     auto epilogue = [&](auto general_tag) {
         constexpr bool GEN = decltype(general_tag)::value;
         auto put_cplx = [&](int64_t i, int64_t j, T re, T im) {
@@ -823,6 +844,24 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
                 update_real<T, !FAST, false>(g, i, j, re);
             }
         };
+        auto pick = [&](int a, int b, int v) {
+            T r = acc[0][b][v];
+#pragma unroll
+            for (int x = 1; x < WMB; ++x) r = (a == x) ? acc[x][b][v] : r;
+            return r;
+        };
+        // general updates per thread: rolled from 64 on
+        constexpr int NCALL = WNB * 4 * (MDBL ? WMB / 2 : WMB) / (NDBL ? 2 : 1);
+        constexpr bool ROLL = GEN && NCALL >= 64;
+        auto rows = [&](int count, auto fn) {
+            if constexpr (ROLL) {
+#pragma unroll 1
+                for (int a = 0; a < count; ++a) fn(a);
+            } else {
+#pragma unroll
+                for (int a = 0; a < count; ++a) fn(a);
+            }
+        };
         const int ml = lane & 15;
 #pragma unroll
         for (int b = 0; b < WNB; ++b) {
@@ -830,29 +869,26 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_gemm_kernel(GemmArgs g) {
             for (int v = 0; v < 4; ++v) {
                 const int nl = acc_row<T>(lane, v);
                 if constexpr (MDBL) {
-#pragma unroll
-                    for (int q = 0; q < WMB / 2; ++q) {
+                    rows(WMB / 2, [&](int q) {
                         const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
                         const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                        put_cplx(i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
-                    }
+                        put_cplx(i, j, pick(2 * q, b, v), pick(2 * q + 1, b, v));
+                    });
                 } else if constexpr (NDBL) {
                     if ((b & 1) == 0) {
-#pragma unroll
-                        for (int a = 0; a < WMB; ++a) {
+                        rows(WMB, [&](int a) {
                             const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                             const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
-                            put_cplx(i, j, acc[a][b][v], acc[a][b + 1][v]);
-                        }
+                            put_cplx(i, j, pick(a, b, v), pick(a, b + 1, v));
+                        });
                     }
                 } else {
-#pragma unroll
-                    for (int a = 0; a < WMB; ++a) {
+                    rows(WMB, [&](int a) {
                         const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
                         const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                        if constexpr (CCPLX) put_cplx(i, j, acc[a][b][v], (T)0);
-                        else put_real(i, j, acc[a][b][v]);
-                    }
+                        if constexpr (CCPLX) put_cplx(i, j, pick(a, b, v), (T)0);
+                        else put_real(i, j, pick(a, b, v));
+                    });
                 }
             }
         }

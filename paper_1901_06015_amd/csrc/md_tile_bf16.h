@@ -40,6 +40,7 @@ struct LayBF {
 // Staging output that writes the hi and lo halves of each FP32 value.
 template <bool MNC, int BMN>
 struct SplitOut {
+    static constexpr bool NARROW = true;  // every value converted to bf16
     typedef LayBF<MNC, BMN> L;
     __bf16 *hi, *lo;
     __device__ __forceinline__ void put(int kk, int mm, float v) const {
@@ -70,6 +71,7 @@ __device__ __forceinline__ bf16x4 lds_read_tr16(const __bf16 *p) {
 // Staging output that rounds each FP32 value to binary16 (nearest even).
 template <bool MNC, int BMN>
 struct HalfOut {
+    static constexpr bool NARROW = true;  // every value converted to binary16
     typedef LayBF<MNC, BMN> L;
     __bf16 *plane;  // 16-bit LDS storage, written as binary16
     __device__ __forceinline__ void put(int kk, int mm, float v) const {
@@ -148,8 +150,11 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
             lb.store_to(SplitOut<BMNC, C::BN>{sB[buf][0], sB[buf][NPL - 1]});
         }
     };
-    // One LDS tile = one 32-deep step: 3 bf16 MFMAs per 16x16 block.
-    auto tile = [&](int cur, bool store_next) {
+    // One LDS tile = one 32-deep step: 3 bf16 MFMAs per 16x16 block.  With
+    // store_next the staged registers of tile t+1 go to the other buffer
+    // (last read before the previous barrier) and the loads of tile
+    // `next_load` are issued before the MFMAs, which they then overlap.
+    auto tile = [&](int cur, bool store_next, int next_load) {
         bf16x8 ah[WMB], al[WMB], bh[WNB], bl[WNB];
 #pragma unroll
         for (int i = 0; i < WMB; ++i) {
@@ -162,6 +167,10 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
             if constexpr (!H16) bl[i] = read_bf16_frag<BMNC, C::BN>(sB[cur][NPL - 1], lane, wn0, i);
         }
         if (store_next) stage_out(cur ^ 1);
+        if (next_load < nk) {
+            la.load(next_load);
+            lb.load(next_load);
+        }
 #pragma unroll
         for (int a = 0; a < WMB; ++a)
 #pragma unroll
@@ -186,48 +195,69 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     }
     int t = 0;
     for (; t + 1 < nk; ++t) {
-        tile(t & 1, true);
+        tile(t & 1, true, t + 2);
         __syncthreads();
-        if (t + 2 < nk) {
-            la.load(t + 2);
-            lb.load(t + 2);
-        }
     }
-    tile(t & 1, false);
+    tile(t & 1, false, nk);
 
-    const int ml = lane & 15;
+    // Binary16 C takes the general update (decided once per workgroup), so
+    // the common case keeps the plain update's code.  The general update is
+    // too large to inline at every accumulator of the wide tiles: there the
+    // loop over row blocks stays rolled and picks its accumulator with
+    // selects (an indexed access would put the accumulators in scratch).
+    auto epilogue = [&](auto general_tag) {
+        constexpr bool GEN = decltype(general_tag)::value;
+        auto pick = [&](int a, int b, int v) {
+            float r = acc[0][b][v];
 #pragma unroll
-    for (int b = 0; b < WNB; ++b) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int nl = acc_row<float>(lane, v);
-            if constexpr (MDBL) {
-#pragma unroll
-                for (int q = 0; q < WMB / 2; ++q) {
-                    const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
-                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    update_cplx<float, !FAST, true>(g, i, j, acc[2 * q][b][v], acc[2 * q + 1][b][v]);
-                }
-            } else if constexpr (NDBL) {
-                if ((b & 1) == 0) {
-#pragma unroll
-                    for (int a = 0; a < WMB; ++a) {
-                        const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
-                        const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
-                        update_cplx<float, !FAST, true>(g, i, j, acc[a][b][v], acc[a][b + 1][v]);
-                    }
-                }
+            for (int x = 1; x < WMB; ++x) r = (a == x) ? acc[x][b][v] : r;
+            return r;
+        };
+        // general updates per thread: rolled from 64 on
+        constexpr int NCALL = WNB * 4 * (MDBL ? WMB / 2 : WMB) / (NDBL ? 2 : 1);
+        constexpr bool ROLL = GEN && NCALL >= 64;
+        auto rows = [&](int count, auto fn) {
+            if constexpr (ROLL) {
+#pragma unroll 1
+                for (int a = 0; a < count; ++a) fn(a);
             } else {
 #pragma unroll
-                for (int a = 0; a < WMB; ++a) {
-                    const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
-                    const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                    if constexpr (CCPLX) update_cplx<float, !FAST, true>(g, i, j, acc[a][b][v], 0.0f);
-                    else update_real<float, !FAST, true>(g, i, j, acc[a][b][v]);
+                for (int a = 0; a < count; ++a) fn(a);
+            }
+        };
+        const int ml = lane & 15;
+#pragma unroll
+        for (int b = 0; b < WNB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int nl = acc_row<float>(lane, v);
+                if constexpr (MDBL) {
+                    rows(WMB / 2, [&](int q) {
+                        const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
+                        const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                        update_cplx<float, !FAST, GEN>(g, i, j, pick(2 * q, b, v), pick(2 * q + 1, b, v));
+                    });
+                } else if constexpr (NDBL) {
+                    if ((b & 1) == 0) {
+                        rows(WMB, [&](int a) {
+                            const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
+                            const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
+                            update_cplx<float, !FAST, GEN>(g, i, j, pick(a, b, v), pick(a, b + 1, v));
+                        });
+                    }
+                } else {
+                    rows(WMB, [&](int a) {
+                        const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
+                        const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
+                        if constexpr (CCPLX) update_cplx<float, !FAST, GEN>(g, i, j, pick(a, b, v), 0.0f);
+                        else update_real<float, !FAST, GEN>(g, i, j, pick(a, b, v));
+                    });
                 }
             }
         }
-    }
+    };
+    if (g.c_half) epilogue(std::true_type{});
+    else epilogue(std::false_type{});
 }
 
 }  // namespace md
