@@ -38,7 +38,6 @@ int bucket_of(int64_t dim) {
 
 int choose_cfg(int prec, int cs, int64_t m_real, int64_t n_real) {
     if (prec == PREC_BF16X3) return GCFG_64;  // the only BF16x3 shape of the grouped kernel
-    if (GROUPED_OCC >= 3 && prec == PREC_D) return GCFG_64;  // no FP64 128 shape at this occupancy
     std::lock_guard<std::mutex> lk(g_table_mu);
     if (!g_table_init) default_table();
     return g_table[prec][cs][bucket_of(std::max(m_real, n_real))];

@@ -7,7 +7,8 @@ namespace md {
 // The persistent kernel.  `hdr[0]` is the tile counter (zeroed by the host's
 // upload of the table); every workgroup exits once the counter passes
 // `ntiles`.
-__global__ __launch_bounds__(NT, GROUPED_OCC) void md_grouped_kernel(const GDesc *descs, const GTile *tiles, int ntiles,
+__global__ __launch_bounds__(GNT, GROUPED_WAVES) void md_grouped_kernel(const GDesc *__restrict__ descs,
+                                                                     const GTile *__restrict__ tiles, int ntiles,
                                                             int *hdr) {
     __shared__ __attribute__((aligned(16))) char smem[GROUPED_SMEM];
     __shared__ int s_t;
@@ -30,23 +31,21 @@ __global__ __launch_bounds__(NT, GROUPED_OCC) void md_grouped_kernel(const GDesc
         // precisions of A and B); everything else is decoded per tile
         const int sel = ((d.prec * GCFG_COUNT + d.cfg) * 2 + d.g.a_dbl) * 2 + d.g.b_dbl;
 #define MD_GSEL(p, c, ad, bd) ((((p) * GCFG_COUNT + (c)) * 2 + (ad)) * 2 + (bd))
-#define MD_GCASES(p, c, T, WB)                                                                              \
-    case MD_GSEL(p, c, 0, 0): grouped_tile<T, WB, false, false>(d, tm, tn, smem); break;                   \
-    case MD_GSEL(p, c, 0, 1): grouped_tile<T, WB, false, true>(d, tm, tn, smem); break;                    \
-    case MD_GSEL(p, c, 1, 0): grouped_tile<T, WB, true, false>(d, tm, tn, smem); break;                    \
-    case MD_GSEL(p, c, 1, 1): grouped_tile<T, WB, true, true>(d, tm, tn, smem); break;
+#define MD_GCASES(p, c, T, SH)                                                                              \
+    case MD_GSEL(p, c, 0, 0): grouped_tile<T, SH, false, false>(d, tm, tn, smem); break;                   \
+    case MD_GSEL(p, c, 0, 1): grouped_tile<T, SH, false, true>(d, tm, tn, smem); break;                    \
+    case MD_GSEL(p, c, 1, 0): grouped_tile<T, SH, true, false>(d, tm, tn, smem); break;                    \
+    case MD_GSEL(p, c, 1, 1): grouped_tile<T, SH, true, true>(d, tm, tn, smem); break;
 #define MD_GCASES_BF(c)                                                                                     \
-    case MD_GSEL(PREC_BF16X3, c, 0, 0): grouped_tile_bf16x3<2, false, false>(d, tm, tn, smem); break;      \
-    case MD_GSEL(PREC_BF16X3, c, 0, 1): grouped_tile_bf16x3<2, false, true>(d, tm, tn, smem); break;       \
-    case MD_GSEL(PREC_BF16X3, c, 1, 0): grouped_tile_bf16x3<2, true, false>(d, tm, tn, smem); break;       \
-    case MD_GSEL(PREC_BF16X3, c, 1, 1): grouped_tile_bf16x3<2, true, true>(d, tm, tn, smem); break;
+    case MD_GSEL(PREC_BF16X3, c, 0, 0): grouped_tile_bf16x3<false, false>(d, tm, tn, smem); break;         \
+    case MD_GSEL(PREC_BF16X3, c, 0, 1): grouped_tile_bf16x3<false, true>(d, tm, tn, smem); break;          \
+    case MD_GSEL(PREC_BF16X3, c, 1, 0): grouped_tile_bf16x3<true, false>(d, tm, tn, smem); break;          \
+    case MD_GSEL(PREC_BF16X3, c, 1, 1): grouped_tile_bf16x3<true, true>(d, tm, tn, smem); break;
         switch (sel) {
-            MD_GCASES(PREC_S, GCFG_64, float, 2)
-            MD_GCASES(PREC_S, GCFG_128, float, 4)
-            MD_GCASES(PREC_D, GCFG_64, double, 2)
-#if MD_GOCC < 3
-            MD_GCASES(PREC_D, GCFG_128, double, 4)
-#endif
+            MD_GCASES(PREC_S, GCFG_64, float, GS_S64)
+            MD_GCASES(PREC_S, GCFG_128, float, GS_S128)
+            MD_GCASES(PREC_D, GCFG_64, double, GS_D64)
+            MD_GCASES(PREC_D, GCFG_128, double, GS_D128)
             // BF16x3 has a single (64x64) shape in the grouped kernel
             MD_GCASES_BF(GCFG_64)
             MD_GCASES_BF(GCFG_128)
@@ -60,7 +59,7 @@ __global__ __launch_bounds__(NT, GROUPED_OCC) void md_grouped_kernel(const GDesc
 
 void launch_grouped_kernel(int grid, hipStream_t s, const GDesc *descs, const GTile *tiles, int ntiles,
                            int *hdr) {
-    hipLaunchKernelGGL(md_grouped_kernel, dim3(grid), dim3(NT), 0, s, descs, tiles, ntiles, hdr);
+    hipLaunchKernelGGL(md_grouped_kernel, dim3(grid), dim3(GNT), 0, s, descs, tiles, ntiles, hdr);
 }
 
 }  // namespace md
