@@ -258,26 +258,44 @@ int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream);
 int mdgemm_grouped_noalloc(int64_t count, const md_gemm_desc *descs, void *stream);
 
 /*
- * Tile-shape table of the grouped kernel: for each computation precision
- * (md_comp S, D or S_BF16X3), domain case (md_case) and size bucket (by the
- * larger dimension of the real product the case lowers to: 0: <=64, 1: <=128,
- * 2: <=256, 3: <=512, 4: <=1024, 5: larger) the workgroup tile edge, 64 or
- * 128 (BF16x3 products always use 64).  The autotuner measures both and
- * writes a text table, one entry per
- * line: "comp case bucket tile" (comp s|d|bf16x3, case 0|1a|1b|1c|2ab|2ac|2bc|3),
- * '#' comments.
+ * Tile configurations of the grouped kernel: the workgroup tile of the real
+ * product (m' x n') and its k-tile depth (double / single computation
+ * precision), each run by 8 waves.
+ */
+enum md_gtile {
+    MD_GTILE_64x64 = 0,       /* 64 x 64, k-tile 16 / 32, 2 x 2 waves in two k-groups */
+    MD_GTILE_128x128 = 1,     /* 128 x 128, k-tile 8 / 16, 2 x 4 waves */
+    MD_GTILE_128x64 = 2,      /* 128 x 64, k-tile 16 / 32, 4 x 2 waves */
+    MD_GTILE_64x128 = 3,      /* 64 x 128, k-tile 16 / 32, 2 x 4 waves */
+    MD_GTILE_64x64_DEEPK = 4, /* 64 x 64, k-tile 32 / 64, 2 x 2 waves in two k-groups */
+    MD_GTILE_COUNT = 5
+};
+
+/*
+ * Tile table of the grouped kernel: for each computation precision (md_comp
+ * S, D or S_BF16X3), domain case (md_case) and pair of size buckets of the
+ * real product the case lowers to (m' and n' each: 0: <=64, 1: <=128,
+ * 2: <=256, 3: <=512, 4: larger) the md_gtile configuration.  BF16x3 products
+ * always use MD_GTILE_64x64.  Built-in default: per dimension, a 64-wide tile
+ * up to bucket 2 and a 128-wide one above.  The autotuner measures the
+ * configurations in context and writes a text table, one entry per line:
+ * "comp case bucket_m bucket_n config" (comp s|d|bf16x3, case
+ * 0|1a|1b|1c|2ab|2ac|2bc|3, config 64x64|128x128|128x64|64x128|64x64k), '#'
+ * comments.
  *
- * mdgemm_tune_load: reset to the built-in defaults, then apply the file at
- *   `path` (NULL: defaults only).  Returns 0, or MD_ERR_STATE (table
- *   unchanged) if the file is missing or malformed.
- * mdgemm_tune_set: set one entry; returns 0 or MD_ERR_STATE for an invalid
- *   entry.
- * mdgemm_tune_get: the current tile edge of one entry, or -1 if invalid.
+ * mdgemm_tune_load: the built-in defaults with the entries of the file at
+ *   `path` applied become the table (NULL: the defaults alone).  Returns 0,
+ *   or MD_ERR_STATE with the table unchanged if the file is missing or
+ *   malformed.
+ * mdgemm_tune_set: set one entry to an md_gtile value; returns 0 or
+ *   MD_ERR_STATE for an invalid entry.
+ * mdgemm_tune_get: the md_gtile value of one entry, or -1 if invalid.
  * The table is process-wide and guarded by a lock.
  */
+#define MD_TUNE_BUCKETS 5
 int mdgemm_tune_load(const char *path);
-int mdgemm_tune_set(int comp, int domain_case, int bucket, int tile);
-int mdgemm_tune_get(int comp, int domain_case, int bucket);
+int mdgemm_tune_set(int comp, int domain_case, int bucket_m, int bucket_n, int config);
+int mdgemm_tune_get(int comp, int domain_case, int bucket_m, int bucket_n);
 
 /* Human-readable text for a status code. */
 const char *mdgemm_strerror(int status);

@@ -74,9 +74,9 @@ def lib():
         L.mdgemm_grouped_noalloc.restype = ci
         L.mdgemm_tune_load.argtypes = [ctypes.c_char_p]
         L.mdgemm_tune_load.restype = ci
-        L.mdgemm_tune_set.argtypes = [ci, ci, ci, ci]
+        L.mdgemm_tune_set.argtypes = [ci, ci, ci, ci, ci]
         L.mdgemm_tune_set.restype = ci
-        L.mdgemm_tune_get.argtypes = [ci, ci, ci]
+        L.mdgemm_tune_get.argtypes = [ci, ci, ci, ci]
         L.mdgemm_tune_get.restype = ci
         L.mdgemm_strerror.argtypes = [ci]
         L.mdgemm_strerror.restype = ctypes.c_char_p
@@ -168,11 +168,27 @@ def tune_load(path):
     return lib().mdgemm_tune_load(None if path is None else path.encode())
 
 
-def tune_set(comp, case, bucket, tile):
+# Grouped tile configurations (md_gtile), by their table-file names.
+GTILE_NAMES = ("64x64", "128x128", "128x64", "64x128", "64x64k")
+TUNE_BUCKETS = 5
+
+
+def tune_set(comp, case, bucket_m, bucket_n, config):
+    """Set one tile-table entry; `config` is an md_gtile value or its name."""
+    cfg = GTILE_NAMES.index(config) if isinstance(config, str) else config
     return lib().mdgemm_tune_set(comp_tag(comp), CASE_NAMES.index(case) if isinstance(case, str) else case,
-                                 bucket, tile)
+                                 bucket_m, bucket_n, cfg)
 
 
-def tune_get(comp, case, bucket):
+def tune_get(comp, case, bucket_m, bucket_n):
+    """The md_gtile value of one tile-table entry (-1 if invalid)."""
     return lib().mdgemm_tune_get(comp_tag(comp), CASE_NAMES.index(case) if isinstance(case, str) else case,
-                                 bucket)
+                                 bucket_m, bucket_n)
+
+
+def tune_bucket(dim):
+    """Size bucket of a real-product dimension (<=64, <=128, <=256, <=512, larger)."""
+    b, lim = 0, 64
+    while b < TUNE_BUCKETS - 1 and dim > lim:
+        b, lim = b + 1, lim * 2
+    return b

@@ -1,22 +1,30 @@
-"""Autotuner for the grouped kernel's tile-shape table.
+"""Autotuner for the grouped kernel's tile table.
 
 The table maps (computation precision s/d, domain case, size bucket of the
-larger real-product dimension: <=64, <=128, <=256, <=512, <=1024, larger) to
-a tile edge (64 or 128).  Tiles of one grouped launch share the GPU, so the
-best shape for a product depends on the mix it runs in.  The tuner therefore
-works in context: it draws a representative training batch (by default the
-batching workload's distribution -- 512 products, m, n, k log-uniform in
-[16, 1024], combination and precision uniform over the 128 cases -- with its
-own seed), then does coordinate descent over the table entries that the batch
-touches, flipping one entry at a time and keeping a flip only if the measured
-time of the whole grouped launch improves by more than 1 %.  Entries the batch
-does not touch keep their defaults.  The result is a text table for
-mdgemm_tune_load():
+real product's m', size bucket of its n' -- each <=64, <=128, <=256, <=512,
+larger) to one of the grouped kernel's tile configurations: the workgroup
+tile (64x64, 128x128, 128x64, 64x128), its wave arrangement (2x2 waves in two
+k-groups, or 2x4 / 4x2 waves) and its k-tile depth (the 64x64 tile also
+comes with a doubled k-tile, "64x64k").  Tiles of one grouped launch share
+the GPU, so the best configuration for a product depends on the mix it runs
+in.  The tuner therefore works in context: it draws a representative
+training batch (by default the batching workload's distribution -- 512
+products, m, n, k log-uniform in [16, 1024], combination and precision
+uniform over the 128 cases -- with its own seed), then does coordinate
+descent over the table entries that the batch touches: for one entry at a
+time it times the whole grouped launch with each configuration (interleaved
+repetitions, medians) and keeps the best only if it beats the entry's
+current configuration by more than 1 %.
+Entries the batch does not touch keep their defaults.  The result is a text
+table for mdgemm_tune_load():
 
     python -m paper_1901_06015_amd.autotune --out paper_1901_06015_amd/tune_table.txt
 
-Every measurement is a real launch on the GPU (HIP events, best of a few
-repetitions); nothing is modelled.
+Every measurement is a real launch on the GPU (HIP events, median of a few
+repetitions); nothing is modelled.  Not searched: the MFMA instruction shape
+(FP64 has one dense 16x16 shape; the FP32 32x32 shape has the same rate) and
+split k (a grouped tile is one workgroup's; products long in k keep whole
+k ranges, the plain path splits them).
 """
 import argparse
 import itertools
@@ -28,9 +36,6 @@ import numpy as np
 from . import _lib, inputs
 
 CASES = ("0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3")
-BUCKET_EDGES = (64, 128, 256, 512, 1024, 2048)
-
-
 def combos_of_case(case):
     """Storage combinations (C, A, B) that fall in a domain case."""
     out = []
@@ -60,60 +65,85 @@ def training_batch(count=512, seed=777, lo=16, hi=1024):
         descs.append(_lib.make_desc("N", "N", m, n, k, 1.0, A.data_ptr(), ta, m, B.data_ptr(), tb, k, 1.0,
                                     C.data_ptr(), tc, m, comp))
         st, pl = _lib.mdgemm_plan("N", "N", m, n, k, 1.0, 1, ta, m, 1, tb, k, 1.0, 1, tc, m, comp)
-        big = max(pl["m_real"], pl["n_real"])
-        bucket = next((b for b, e in enumerate(BUCKET_EDGES[:-1]) if big <= e), len(BUCKET_EDGES) - 1)
-        touched.add((comp, pl["case"], bucket))
+        touched.add((comp, pl["case"], _lib.tune_bucket(pl["m_real"]), _lib.tune_bucket(pl["n_real"])))
     return keep, descs, touched
+
+
+def _timed_launch(descs, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    if _lib.mdgemm_grouped(descs, stream) != 0:
+        raise RuntimeError("grouped launch failed")
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
 
 
 def time_grouped_median(descs, reps=7):
     import torch
     stream = torch.cuda.current_stream().cuda_stream
-    if _lib.mdgemm_grouped(descs, stream) != 0:
-        raise RuntimeError("grouped launch failed")
-    torch.cuda.synchronize()
-    ts = []
+    _timed_launch(descs, stream)
+    return float(np.median([_timed_launch(descs, stream) for _ in range(reps)]))
+
+
+def compare_configs(descs, entry, configs, reps=7):
+    """Median launch time of the whole batch with `entry` set to each of
+    `configs`, measured interleaved (one launch per configuration in turn,
+    `reps` rounds) so that clock and thermal drift hit every candidate alike."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    comp, case, bm, bn = entry
+    times = {c: [] for c in configs}
     for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        _lib.mdgemm_grouped(descs, stream)
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1) / 1e3)
-    return float(np.median(ts))
+        for c in configs:
+            _lib.tune_set(comp, case, bm, bn, c)
+            times[c].append(_timed_launch(descs, stream))
+    return {c: float(np.median(t)) for c, t in times.items()}
 
 
 def tune(out_path, seed=777, passes=2, verbose=True):
     _lib.lib()
     _lib.tune_load(None)
     keep, descs, touched = training_batch(seed=seed)
-    best = time_grouped_median(descs)
+    for _ in range(20):  # warm up clocks, caches and the upload staging
+        time_grouped_median(descs, reps=1)
+    start = time_grouped_median(descs, reps=15)
     if verbose:
-        print("# start (defaults): %.4f ms, %d entries touched" % (best * 1e3, len(touched)), flush=True)
+        print("# start (defaults): %.4f ms, %d entries touched" % (start * 1e3, len(touched)), flush=True)
+    configs = list(range(len(_lib.GTILE_NAMES)))
     for p in range(passes):
         changed = False
-        for comp, case, bucket in sorted(touched):
-            cur = _lib.tune_get(comp, case, bucket)
-            alt = 64 if cur == 128 else 128
-            _lib.tune_set(comp, case, bucket, alt)
-            t = time_grouped_median(descs)
-            if t < best * 0.99:
-                best = t
+        for entry in sorted(touched):
+            comp, case, bm, bn = entry
+            cur = _lib.tune_get(comp, case, bm, bn)
+            med = compare_configs(descs, entry, configs)
+            best_cfg = min(configs, key=lambda c: med[c])
+            if med[best_cfg] >= med[cur] * 0.99:
+                best_cfg = cur
+            _lib.tune_set(comp, case, bm, bn, best_cfg)
+            if best_cfg != cur:
                 changed = True
                 if verbose:
-                    print("# pass %d: %s %s %d -> %d: %.4f ms" % (p, comp, case, bucket, alt, t * 1e3), flush=True)
-            else:
-                _lib.tune_set(comp, case, bucket, cur)
+                    print("# pass %d: %s %s %d %d: %s -> %s (%.4f -> %.4f ms)" % (
+                        p, comp, case, bm, bn, _lib.GTILE_NAMES[cur], _lib.GTILE_NAMES[best_cfg],
+                        med[cur] * 1e3, med[best_cfg] * 1e3), flush=True)
         if not changed:
             break
-    lines = ["# grouped-kernel tile-shape table written by paper_1901_06015_amd.autotune",
-             "# tuned in context on a seeded training batch (seed %d): %.4f ms per grouped launch" % (seed, best * 1e3),
-             "# comp case bucket tile"]
+    best = time_grouped_median(descs, reps=15)
+    if verbose:
+        print("# tuned: %.4f ms (defaults %.4f ms)" % (best * 1e3, start * 1e3), flush=True)
+    lines = ["# grouped-kernel tile table written by paper_1901_06015_amd.autotune",
+             "# tuned in context on a seeded training batch (seed %d): %.4f ms per grouped launch "
+             "(built-in rule %.4f ms)" % (seed, best * 1e3, start * 1e3),
+             "# comp case bucket_m bucket_n config"]
     for comp in ("s", "d"):
         for case in CASES:
-            for b in range(len(BUCKET_EDGES)):
-                lines.append("%s %s %d %d" % (comp, case, b, _lib.tune_get(comp, case, b)))
+            for bm in range(_lib.TUNE_BUCKETS):
+                for bn in range(_lib.TUNE_BUCKETS):
+                    lines.append("%s %s %d %d %s" % (comp, case, bm, bn,
+                                                     _lib.GTILE_NAMES[_lib.tune_get(comp, case, bm, bn)]))
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     del keep

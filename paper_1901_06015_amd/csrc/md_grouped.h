@@ -17,8 +17,13 @@
 
 namespace md {
 
-// Tile shapes of the grouped kernel (real-product workgroup tile).
-enum { GCFG_64 = 0, GCFG_128 = 1, GCFG_COUNT = 2 };
+// Tile configurations of the grouped kernel (the md_gtile values of
+// mdgemm.h): real-product workgroup tile and k-tile depth.
+enum { GCFG_64 = MD_GTILE_64x64, GCFG_128 = MD_GTILE_128x128, GCFG_128x64 = MD_GTILE_128x64,
+       GCFG_64x128 = MD_GTILE_64x128, GCFG_64K = MD_GTILE_64x64_DEEPK, GCFG_COUNT = MD_GTILE_COUNT };
+// workgroup tile edges along m' and n' of each configuration
+constexpr int gcfg_bm(int c) { return (c == GCFG_128 || c == GCFG_128x64) ? 128 : 64; }
+constexpr int gcfg_bn(int c) { return (c == GCFG_128 || c == GCFG_64x128) ? 128 : 64; }
 
 struct GDesc {
     GemmArgs g;
@@ -62,17 +67,26 @@ struct GShape {
     // the k-groups' partial sums go through the (then free) staging LDS
     static_assert(KG == 1 || (KG - 1) * (8 / KG) * 64 * WMB * WNB * 4 * (int)sizeof(T) <= SMEM, "reduction");
 };
+// the shapes of each configuration (GCFG_*), single and double
 typedef GShape<float, 64, 64, 2, 2, 32> GS_S64;
 typedef GShape<float, 128, 128, 2, 4, 16> GS_S128;
+typedef GShape<float, 128, 64, 4, 2, 32> GS_S128x64;
+typedef GShape<float, 64, 128, 2, 4, 32> GS_S64x128;
+typedef GShape<float, 64, 64, 2, 2, 64> GS_S64K;
 typedef GShape<double, 64, 64, 2, 2, 16> GS_D64;
 typedef GShape<double, 128, 128, 2, 4, 8> GS_D128;
+typedef GShape<double, 128, 64, 4, 2, 16> GS_D128x64;
+typedef GShape<double, 64, 128, 2, 4, 16> GS_D64x128;
+typedef GShape<double, 64, 64, 2, 2, 32> GS_D64K;
 // BF16x3: 64 x 64 tiles, four bf16 planes (A hi/lo, B hi/lo) of BK3 = 64 k
 // each per stage, one 16x16x32 step per k-group.
 constexpr int BK3 = 64, LDW3 = 64 + 4;
 constexpr int BF16X3_GROUPED_SMEM = 2 * 4 * BK3 * LDW3 * 2;
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int GROUPED_SMEM = cmax(cmax(cmax(GS_S64::SMEM, GS_S128::SMEM), cmax(GS_D64::SMEM, GS_D128::SMEM)),
-                                  BF16X3_GROUPED_SMEM);
+constexpr int GROUPED_SMEM =
+    cmax(cmax(cmax(cmax(GS_S64::SMEM, GS_S128::SMEM), cmax(GS_S128x64::SMEM, GS_S64x128::SMEM)),
+              cmax(cmax(GS_D64::SMEM, GS_D128::SMEM), cmax(GS_D128x64::SMEM, GS_D64x128::SMEM))),
+         cmax(cmax(GS_S64K::SMEM, GS_D64K::SMEM), BF16X3_GROUPED_SMEM));
 static_assert(2 * GROUPED_SMEM <= 160 * 1024, "two grouped workgroups per CU");
 
 // Runtime description of one staged operand (A' or B').

@@ -15,18 +15,30 @@
 namespace md {
 namespace {
 
-// Tile-shape table: for (computation precision, domain case, size bucket) the
-// grouped kernel's tile shape.  Buckets are by the larger dimension of the
-// real product: <=64, <=128, <=256, <=512, <=1024, larger.
-constexpr int NBUCKET = 6;
-int g_table[3][8][NBUCKET];
+// Tile table: for (computation precision, domain case, size bucket of m',
+// size bucket of n') the grouped kernel's tile configuration (GCFG_*).
+// Buckets: <=64, <=128, <=256, <=512, larger.
+constexpr int NBUCKET = MD_TUNE_BUCKETS;
+int g_table[3][8][NBUCKET][NBUCKET];
 std::mutex g_table_mu;
 bool g_table_init = false;
 
-void default_table() {
+// Built-in rule: per dimension a 64-wide tile up to 256, 128 above.
+int default_cfg(int prec, int bm, int bn) {
+    if (prec == PREC_BF16X3) return GCFG_64;
+    const bool wm = bm > 2, wn = bn > 2;
+    return wm ? (wn ? GCFG_128 : GCFG_128x64) : (wn ? GCFG_64x128 : GCFG_64);
+}
+
+void fill_defaults(int (&t)[3][8][NBUCKET][NBUCKET]) {
     for (int p = 0; p < 3; ++p)
         for (int c = 0; c < 8; ++c)
-            for (int b = 0; b < NBUCKET; ++b) g_table[p][c][b] = (b <= 2 || p == PREC_BF16X3) ? GCFG_64 : GCFG_128;
+            for (int bm = 0; bm < NBUCKET; ++bm)
+                for (int bn = 0; bn < NBUCKET; ++bn) t[p][c][bm][bn] = default_cfg(p, bm, bn);
+}
+
+void default_table() {
+    fill_defaults(g_table);
     g_table_init = true;
 }
 
@@ -40,7 +52,7 @@ int choose_cfg(int prec, int cs, int64_t m_real, int64_t n_real) {
     if (prec == PREC_BF16X3) return GCFG_64;  // the only BF16x3 shape of the grouped kernel
     std::lock_guard<std::mutex> lk(g_table_mu);
     if (!g_table_init) default_table();
-    return g_table[prec][cs][bucket_of(std::max(m_real, n_real))];
+    return g_table[prec][cs][bucket_of(m_real)][bucket_of(n_real)];
 }
 
 int g_num_cu = 0;
@@ -150,8 +162,8 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
             e.kind = 0;
             const int64_t mr = x.m * (L.mdbl ? 2 : 1), nr = x.n * (L.ndbl ? 2 : 1);
             e.cfg = choose_cfg(d.prec, d.cs, mr, nr);
-            const int edge = e.cfg == GCFG_64 ? 64 : 128;
-            const int64_t tmn_a = L.mdbl ? edge / 2 : edge, tmn_b = L.ndbl ? edge / 2 : edge;
+            const int bm = gcfg_bm(e.cfg), bn = gcfg_bn(e.cfg);
+            const int64_t tmn_a = L.mdbl ? bm / 2 : bm, tmn_b = L.ndbl ? bn / 2 : bn;
             e.tiles_m = (int)((x.m + tmn_a - 1) / tmn_a);
             e.tiles_n = (int)((x.n + tmn_b - 1) / tmn_b);
         }
@@ -159,10 +171,9 @@ int grouped_enqueue(int64_t count, const md_gemm_desc *descs, const void *const 
         gd.push_back(e);
         // estimated cost of one tile: its real-product flops, weighted by the
         // computation precision's MFMA rate (FP64 is half FP32; BF16x3 ~1/2)
-        const int edge = e.kind == 1 ? 64 : (e.cfg == GCFG_64 ? 64 : 128);
+        const double area = e.kind == 1 ? 64.0 * 64.0 : (double)gcfg_bm(e.cfg) * gcfg_bn(e.cfg);
         const double kr = (double)x.k * (L.kdbl ? 2 : 1);
-        const double w = e.kind == 1 ? (double)edge * edge
-                                     : (double)edge * edge * kr * (d.prec == PREC_D ? 2.0 : (d.prec == PREC_S ? 1.0 : 0.5));
+        const double w = e.kind == 1 ? area : area * kr * (d.prec == PREC_D ? 2.0 : (d.prec == PREC_S ? 1.0 : 0.5));
         work.push_back(w);
         ntiles64 += (int64_t)e.tiles_m * e.tiles_n;
         (void)di;
@@ -301,64 +312,78 @@ int mdgemm_grouped_noalloc(int64_t count, const md_gemm_desc *descs, void *strea
     return md::grouped_enqueue(count, descs, nullptr, stream, nullptr, true);
 }
 
-// Tile-shape table file: one entry per line, "comp case bucket cfg" with comp
-// in {s, d, bf16x3}, case in {0, 1a, 1b, 1c, 2ab, 2ac, 2bc, 3}, bucket 0..5
-// (larger real-product dimension <= 64, 128, 256, 512, 1024, larger) and cfg
-// in {64, 128}; '#' starts a comment.  Entries not listed keep their value.
+// Tile table file: one entry per line, "comp case bucket_m bucket_n config"
+// with comp in {s, d, bf16x3}, case in {0, 1a, 1b, 1c, 2ab, 2ac, 2bc, 3},
+// buckets 0..4 and config one of the names below; '#' starts a comment.
+// Entries not listed keep their default.
+static const char *const kCfgNames[GCFG_COUNT] = {"64x64", "128x128", "128x64", "64x128", "64x64k"};
+
+static int prec_of_comp(int comp) {
+    return comp == MD_COMP_S ? PREC_S : comp == MD_COMP_D ? PREC_D : comp == MD_COMP_S_BF16X3 ? PREC_BF16X3 : -1;
+}
+
+static bool entry_ok(int p, int c, int bm, int bn, int cfg) {
+    return p >= 0 && c >= 0 && c < 8 && bm >= 0 && bm < NBUCKET && bn >= 0 && bn < NBUCKET && cfg >= 0 &&
+           cfg < GCFG_COUNT && (p != PREC_BF16X3 || cfg == GCFG_64);
+}
+
 int mdgemm_tune_load(const char *path) {
     std::lock_guard<std::mutex> lk(g_table_mu);
-    default_table();
-    if (!path) return MD_OK;
+    if (!path) {
+        default_table();
+        return MD_OK;
+    }
     FILE *f = fopen(path, "r");
     if (!f) return MD_ERR_STATE;
     static const char *cases[8] = {"0", "1a", "1b", "1c", "2ab", "2ac", "2bc", "3"};
-    int tmp[3][8][NBUCKET];
-    memcpy(tmp, g_table, sizeof(tmp));
+    int tmp[3][8][NBUCKET][NBUCKET];
+    fill_defaults(tmp);
     char line[256];
     int bad = 0;
     while (fgets(line, sizeof(line), f)) {
         char *h = strchr(line, '#');
         if (h) *h = 0;
-        char comp[32], cs[32];
-        int bucket, cfg;
-        if (sscanf(line, "%31s %31s %d %d", comp, cs, &bucket, &cfg) != 4) {
+        char comp[32], cs[32], cfgname[32];
+        int bm, bn;
+        if (sscanf(line, "%31s %31s %d %d %31s", comp, cs, &bm, &bn, cfgname) != 5) {
             if (sscanf(line, "%31s", comp) == 1) bad = 1;
             continue;
         }
-        int p = !strcmp(comp, "s") ? PREC_S : !strcmp(comp, "d") ? PREC_D : !strcmp(comp, "bf16x3") ? PREC_BF16X3 : -1;
-        int c = -1;
+        const int p = !strcmp(comp, "s") ? PREC_S : !strcmp(comp, "d") ? PREC_D
+                    : !strcmp(comp, "bf16x3") ? PREC_BF16X3 : -1;
+        int c = -1, cfg = -1;
         for (int i = 0; i < 8; ++i)
             if (!strcmp(cs, cases[i])) c = i;
-        if (p < 0 || c < 0 || bucket < 0 || bucket >= NBUCKET || (cfg != 64 && cfg != 128) ||
-            (p == PREC_BF16X3 && cfg != 64)) {
+        for (int i = 0; i < GCFG_COUNT; ++i)
+            if (!strcmp(cfgname, kCfgNames[i])) cfg = i;
+        if (!entry_ok(p, c, bm, bn, cfg)) {
             bad = 1;
             continue;
         }
-        tmp[p][c][bucket] = cfg == 64 ? GCFG_64 : GCFG_128;
+        tmp[p][c][bm][bn] = cfg;
     }
     fclose(f);
     if (bad) return MD_ERR_STATE;
     memcpy(g_table, tmp, sizeof(tmp));
+    g_table_init = true;
     return MD_OK;
 }
 
-int mdgemm_tune_set(int comp, int domain_case, int bucket, int tile) {
+int mdgemm_tune_set(int comp, int domain_case, int bucket_m, int bucket_n, int config) {
     std::lock_guard<std::mutex> lk(g_table_mu);
     if (!g_table_init) default_table();
-    const int p = comp == MD_COMP_S ? PREC_S : comp == MD_COMP_D ? PREC_D : comp == MD_COMP_S_BF16X3 ? PREC_BF16X3 : -1;
-    if (p < 0 || domain_case < 0 || domain_case > 7 || bucket < 0 || bucket >= NBUCKET || (tile != 64 && tile != 128) ||
-        (p == PREC_BF16X3 && tile != 64))
-        return MD_ERR_STATE;
-    g_table[p][domain_case][bucket] = tile == 64 ? GCFG_64 : GCFG_128;
+    const int p = prec_of_comp(comp);
+    if (!entry_ok(p, domain_case, bucket_m, bucket_n, config)) return MD_ERR_STATE;
+    g_table[p][domain_case][bucket_m][bucket_n] = config;
     return MD_OK;
 }
 
-int mdgemm_tune_get(int comp, int domain_case, int bucket) {
+int mdgemm_tune_get(int comp, int domain_case, int bucket_m, int bucket_n) {
     std::lock_guard<std::mutex> lk(g_table_mu);
     if (!g_table_init) default_table();
-    const int p = comp == MD_COMP_S ? PREC_S : comp == MD_COMP_D ? PREC_D : comp == MD_COMP_S_BF16X3 ? PREC_BF16X3 : -1;
-    if (p < 0 || domain_case < 0 || domain_case > 7 || bucket < 0 || bucket >= NBUCKET) return -1;
-    return g_table[p][domain_case][bucket] == GCFG_64 ? 64 : 128;
+    const int p = prec_of_comp(comp);
+    if (!entry_ok(p, domain_case, bucket_m, bucket_n, 0)) return -1;
+    return g_table[p][domain_case][bucket_m][bucket_n];
 }
 
 }  // extern "C"

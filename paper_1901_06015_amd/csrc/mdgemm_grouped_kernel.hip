@@ -44,11 +44,16 @@ __global__ __launch_bounds__(GNT, GROUPED_WAVES) void md_grouped_kernel(const GD
         switch (sel) {
             MD_GCASES(PREC_S, GCFG_64, float, GS_S64)
             MD_GCASES(PREC_S, GCFG_128, float, GS_S128)
+            MD_GCASES(PREC_S, GCFG_128x64, float, GS_S128x64)
+            MD_GCASES(PREC_S, GCFG_64x128, float, GS_S64x128)
+            MD_GCASES(PREC_S, GCFG_64K, float, GS_S64K)
             MD_GCASES(PREC_D, GCFG_64, double, GS_D64)
             MD_GCASES(PREC_D, GCFG_128, double, GS_D128)
+            MD_GCASES(PREC_D, GCFG_128x64, double, GS_D128x64)
+            MD_GCASES(PREC_D, GCFG_64x128, double, GS_D64x128)
+            MD_GCASES(PREC_D, GCFG_64K, double, GS_D64K)
             // BF16x3 has a single (64x64) shape in the grouped kernel
             MD_GCASES_BF(GCFG_64)
-            MD_GCASES_BF(GCFG_128)
         default: break;
         }
 #undef MD_GCASES_BF

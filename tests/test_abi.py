@@ -322,3 +322,54 @@ def test_small_kernel_choice(monkeypatch):
     assert "small" not in plan(64, 64, 64, comp="bf16x3")["kernel"]
     monkeypatch.setenv("MDGEMM_SMALL", "0")
     assert "small" not in plan(256, 256, 256)["kernel"]
+
+
+def test_tune_table_defaults_set_get_and_rejections():
+    """Host-only tile table of the grouped kernel: the built-in rule, set/get
+    round trips, and the entries it must refuse."""
+    names = _lib.GTILE_NAMES
+    assert _lib.tune_load(None) == 0
+    try:
+        for comp in ("s", "d"):
+            for bm in range(_lib.TUNE_BUCKETS):
+                for bn in range(_lib.TUNE_BUCKETS):
+                    want = {(False, False): "64x64", (True, True): "128x128", (True, False): "128x64",
+                            (False, True): "64x128"}[(bm > 2, bn > 2)]
+                    assert names[_lib.tune_get(comp, "3", bm, bn)] == want
+        assert _lib.tune_get("bf16x3", "0", 4, 4) == names.index("64x64")
+        for cfg in names:
+            assert _lib.tune_set("d", "2ac", 1, 3, cfg) == 0
+            assert _lib.tune_get("d", "2ac", 1, 3) == names.index(cfg)
+        bad = [("s", 8, 0, 0, 0), ("s", 0, _lib.TUNE_BUCKETS, 0, 0), ("s", 0, 0, -1, 0),
+               ("d", 0, 0, 0, len(names)), ("bf16x3", 0, 0, 0, 1), ("h", 0, 0, 0, 0)]
+        for comp, case, bm, bn, cfg in bad:
+            assert _lib.tune_set(comp, case, bm, bn, cfg) == _lib.MD_ERR_STATE
+        assert _lib.tune_get("s", 0, _lib.TUNE_BUCKETS, 0) == -1
+        assert _lib.tune_get("h", 0, 0, 0) == -1
+        # the bucket edges
+        assert [_lib.tune_bucket(d) for d in (1, 64, 65, 128, 129, 256, 257, 512, 513, 10 ** 6)] == \
+            [0, 0, 1, 1, 2, 2, 3, 3, 4, 4]
+    finally:
+        _lib.tune_load(None)
+
+
+def test_tune_table_file_round_trip_and_malformed_files(tmp_path):
+    good = tmp_path / "t.txt"
+    good.write_text("# comment\ns 1c 0 4 128x64   # trailing comment\nd 3 4 4 64x64k\nbf16x3 2ab 2 2 64x64\n")
+    try:
+        assert _lib.tune_load(str(good)) == 0
+        assert _lib.tune_get("s", "1c", 0, 4) == _lib.GTILE_NAMES.index("128x64")
+        assert _lib.tune_get("d", "3", 4, 4) == _lib.GTILE_NAMES.index("64x64k")
+        # entries not listed keep the built-in rule
+        assert _lib.tune_get("d", "3", 0, 0) == _lib.GTILE_NAMES.index("64x64")
+        for text in ("s 1c 0 4 96x96\n", "s 9z 0 0 64x64\n", "d 3 5 0 64x64\n", "bf16x3 0 0 0 128x128\n",
+                     "s 0 0\n"):
+            bad = tmp_path / "bad.txt"
+            bad.write_text(text)
+            assert _lib.tune_load(str(bad)) == _lib.MD_ERR_STATE, text
+            # a failed load leaves the table as it was
+            assert _lib.tune_get("s", "1c", 0, 4) == _lib.GTILE_NAMES.index("128x64")
+        assert _lib.tune_load(str(tmp_path / "missing.txt")) == _lib.MD_ERR_STATE
+        assert _lib.tune_get("d", "3", 4, 4) == _lib.GTILE_NAMES.index("64x64k")
+    finally:
+        _lib.tune_load(None)

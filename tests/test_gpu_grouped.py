@@ -148,19 +148,21 @@ def test_grouped_every_combination_once():
     check_all(entries, keep)
 
 
-def test_grouped_quick_returns_and_both_tile_shapes():
+def test_grouped_quick_returns_and_every_tile_configuration():
+    """Every grouped tile configuration, forced for every entry, against the
+    oracle (ragged tiles along m', n' and k in every configuration)."""
     entries = make_entries(24, seed=9, lo=16, hi=700)
     entries[0]["alpha"] = 0.0
     entries[1]["k"] = 0
     entries[2]["m"] = 0
     entries[3]["n"] = 0
-    for tile in (64, 128):
+    for cfg in _lib.GTILE_NAMES:
         for comp in ("s", "d"):
             for case in range(8):
-                for b in range(6):
-                    assert _lib.tune_set(comp, case, b, tile) == 0
-        assert _lib.tune_set("bf16x3", 0, 0, 128) == _lib.MD_ERR_STATE
-        say("grouped with tile", tile)
+                for bm in range(_lib.TUNE_BUCKETS):
+                    for bn in range(_lib.TUNE_BUCKETS):
+                        assert _lib.tune_set(comp, case, bm, bn, cfg) == 0
+        say("grouped with tile configuration", cfg)
         st, keep = run_grouped(entries)
         assert st == 0
         check_all(entries, keep)
