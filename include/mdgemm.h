@@ -32,10 +32,17 @@
  *     products in a workspace of the library, one per (device, stream):
  *     allocated with hipMallocAsync on that stream when first needed, grown
  *     on demand (the old buffer freed in stream order) and kept until the
- *     process ends, at most about 100 MB per stream.  Calls on one stream may
- *     come from several host threads.  With MDGEMM_SPLITK=0 in the
- *     environment products are never split and mdgemm allocates no device
- *     memory.
+ *     process ends, at most about 100 MB per stream.  A BF16x3 product large
+ *     enough to fill the GPU with 256 x 256 tiles of its real product (at
+ *     least 128 of them and k' >= 256) runs on operands cast, split into
+ *     bf16 planes and packed once per call, in a second workspace of the
+ *     same kind: 4 bytes per element of the real product's padded A' and B'
+ *     (about 0.8 GB for m = n = k = 8192 in case 2ac), at most 8 GiB; when
+ *     it cannot be had the product runs unpacked.  Calls on one stream may
+ *     come from several host threads.  With MDGEMM_SPLITK=0 and
+ *     MDGEMM_PACK=0 in the environment products are never split or packed
+ *     and mdgemm allocates no device memory (MDGEMM_PACK=2 packs every
+ *     qualifying BF16x3 product whatever its size).
  *
  * Return codes: 0 on success; -i when argument i (1-based, in mdgemm's order)
  * is invalid; positive MD_ERR_* codes otherwise (see mdgemm_strerror).
@@ -246,7 +253,7 @@ int mdgemm_grouped(int64_t count, const md_gemm_desc *descs, void *stream);
  *     enqueues nothing;
  *   - products that mdgemm_grouped hands to the plain kernels (large leading
  *     dimensions, binary16, a complex alpha staged into an operand) run
- *     unsplit, so no split-k workspace is taken.
+ *     unsplit and unpacked, so no split-k or packing workspace is taken.
  * It calls no hipMalloc, hipFree or other allocating routine (the host copy
  * of the table is ordinary host memory, consumed by the upload).  Every call
  * on one GPU shares that GPU's array, which keeps the last call's table:

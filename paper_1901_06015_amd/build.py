@@ -37,6 +37,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "--offload-arch=" + ARCH, "-
 SOURCES = [("mdgemm_grouped_kernel.hip", [], "grouped_kernel.o")] + [("mdgemm_kernels.hip", ["-DMD_KT=%d" % t, "-DMD_KCASE=%d" % c], "k_%d_%d.o" % (t, c))
            for t in (1, 0, 2, 3) for c in (7, 4, 5, 6, 0, 1, 2, 3)] + [
     ("mdgemm_launch.hip", [], "launch.o"),
+    ("mdgemm_packed.hip", [], "packed.o"),
     ("mdgemm_grouped.hip", [], "grouped.o"),
     ("mdgemm_api.cpp", [], "api.o"),
     ("md_server.cpp", [], "server.o"),

@@ -76,6 +76,7 @@ struct GemmArgs {
     double scale_re, scale_im;  // alpha under the literal interpretation with C real
     int tiles_m, tiles_n;     // workgroup tiles of the real product
     int small;                // runs on md_small_kernel: 32 x 32 real-product tiles (md_small.h)
+    int packed;               // BF16x3 on packed operands: 256 x 256 real-product tiles (md_pack.h)
     int splits;               // > 1: k split over this many workgroups per tile (plain kernels)
     void *part;               // their partial products: splits x n x m pairs (re, im) of the
                               // computation type, summed and finished by md_split_reduce
@@ -138,11 +139,23 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
                 md_scalar beta, void *C, int dtc, int64_t ldc, int comp,
                 int64_t rsa = 1, int64_t rsb = 1, int64_t rsc = 1);
 
-// Host-side launchers (defined in mdgemm_kernels.hip).
-// may_split false: never split k, so nothing is allocated (the split-k
-// workspace is the plain path's only allocation).
+// Host-side launchers (mdgemm_launch.hip, mdgemm_packed.hip).
+// may_split false: never split k or pack, so nothing is allocated (the split-k
+// and packing workspaces are the plain path's only allocations).
 int launch_gemm(int prec, int cs, const GemmArgs &a, void *stream, int64_t *wg_out, bool may_split = true);
 int launch_small(int prec, int cs, const GemmArgs &a, void *stream);
+// BF16x3 products with at least PACK_MIN_TILES 256 x 256 tiles (half the
+// MI355X's CUs; a constant, so that planning needs no device) and k' >= 256
+// run on packed operands (md_pack.h): the operands are cast, split and packed
+// once into a per-stream workspace of at most PACK_MAX_BYTES, then multiplied
+// with direct-to-LDS copies.  MDGEMM_PACK in the environment: 0 never, 2
+// whenever the product qualifies otherwise (any size), else the size rule
+// (read on every call).  launch_packed returns MD_ERR_BUDGET, having enqueued
+// nothing, when the workspace cannot be had.
+constexpr int PACK_TILE = 256;
+constexpr int64_t PACK_MIN_TILES = 128;
+constexpr size_t PACK_MAX_BYTES = (size_t)8 << 30;
+int launch_packed(int cs, const GemmArgs &a, void *stream);
 int launch_scale(const GemmArgs &a, void *stream);
 void tile_shape(int prec, int cs, bool fast, int *bm, int *bn, int *bk);
 void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len);

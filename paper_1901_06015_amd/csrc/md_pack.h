@@ -1,0 +1,146 @@
+// md_pack.h -- BF16x3 on packed operands, for products large enough to fill
+// the GPU with 256 x 256 tiles.
+//
+// The typecasting pack of Section 5 done once per call instead of once per
+// tile: md_pack_x3_kernel reads each operand of the real product (Figure
+// "mixeddom" lowering, element by element as md_small.h does), casts it to
+// FP32, splits it into bf16 hi = RNE(a) and lo = RNE(a - hi) and writes both
+// planes in the layout the multiply kernel's LDS tiles use.  The multiply
+// kernel then copies packed tiles from HBM straight into LDS (gfx950 direct
+// 16-byte loads, no registers and no conversion in the k loop) and runs the
+// three bf16 MFMAs per block of md_bf16x3_kernel, in the same order on the
+// same values: the two forms give the same bits.
+#pragma once
+#include "md_small.h"
+#include "md_tile_bf16.h"
+
+namespace md {
+
+constexpr int PK_ROWS = 256;                   // rows (m' or n') of a packed block
+constexpr int PK_K = 32;                       // k' of a packed block
+constexpr int PK_BLOCK = PK_ROWS * PK_K * 2;   // bytes of one plane of one block (16 KB)
+
+// Packed layout of an operand X' of the real product (rows along m' for A',
+// along n' for B'; k' the depth), both padded with zeros to whole blocks:
+// block (rb, kb) of plane p (0 = hi, 1 = lo) at byte ((rb * nkb + kb) * 2 +
+// p) * PK_BLOCK.  Inside a block, row r holds its 32 k as four 16-byte chunks;
+// chunk q (k = 8q .. 8q+7) of row r is the 16-byte unit number pk_chunk(r, q):
+// the 16 lanes of an MFMA fragment (rows r0 .. r0+15, one q) then read 16
+// distinct groups of 4 LDS banks.
+__host__ __device__ constexpr int pk_chunk(int r, int q) { return 4 * r + (q ^ ((r >> 2) & 3)); }
+
+// One workgroup per packed block (blockIdx.x = rb * nkb + kb), one thread per
+// row: 32 elements of the real product's operand, cast to FP32 as the
+// staging of md_tile.h does (double -> float rounds to nearest even), split
+// and stored.  Elements outside the matrix are zero.  Threads of consecutive
+// rows read consecutive addresses of an operand stored along m' or n'.
+template <int CS, bool IS_A, bool SDBL>
+__global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *out, int nkb) {
+    typedef SmallOp<float, CS, IS_A, SDBL> Op;
+    const Op op(g);
+    const int rb = (int)(blockIdx.x / (unsigned)nkb), kb = (int)(blockIdx.x % (unsigned)nkb);
+    const int r = threadIdx.x;
+    const int64_t row = (int64_t)rb * PK_ROWS + r, k0 = (int64_t)kb * PK_K;
+    char *hi = out + (int64_t)blockIdx.x * 2 * PK_BLOCK, *lo = hi + PK_BLOCK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        bf16x8 h, l;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            bool valid, neg;
+            uint32_t wlo, whi = 0;
+            op.issue(op.where(row, k0 + 8 * q + j, true, &valid, &neg), &wlo, &whi);
+            const float v = Op::value(wlo, whi, valid, neg);
+            const __bf16 vh = (__bf16)v;
+            h[j] = vh;
+            l[j] = (__bf16)(v - (float)vh);
+        }
+        *(bf16x8 *)(hi + pk_chunk(r, q) * 16) = h;
+        *(bf16x8 *)(lo + pk_chunk(r, q) * 16) = l;
+    }
+}
+
+// The multiply kernel: one 256 x 256 tile of the real product per
+// workgroup, 8 waves of 64 (m') x 128 (n'), one 32-deep k-tile per LDS stage
+// (A' hi, A' lo, B' hi, B' lo: 64 KB), two stages.  Each thread copies 8
+// chunks of 16 bytes per k-tile with direct-to-LDS loads; a wave waits for
+// its own copies of tile t (those of tile t+1 stay in flight) and the
+// barrier makes everyone's visible.  The waits and barriers are written as
+// asm with a memory clobber so that no memory access moves across them.
+constexpr int PX_WGM = 4, PX_WGN = 2;
+constexpr int PX_WMB = PK_ROWS / (16 * PX_WGM), PX_WNB = PK_ROWS / (16 * PX_WGN);  // 4 x 8 blocks per wave
+constexpr int PX_NT = 64 * PX_WGM * PX_WGN;
+constexpr int PX_STAGE = 4 * PK_BLOCK;
+
+template <int CS>
+__global__ __launch_bounds__(PX_NT, 2) void md_packed_x3_kernel(GemmArgs g, const char *pa, const char *pb,
+                                                                int nkb) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    __shared__ __attribute__((aligned(16))) char lds[2 * PX_STAGE];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % PX_WGM) * (PK_ROWS / PX_WGM), wn0 = (wave / PX_WGM) * (PK_ROWS / PX_WGN);
+    int tm, tn;
+    map_tile(blockIdx.x, gridDim.x, g.tiles_m, g.tiles_n, &tm, &tn);
+    // this tile's row blocks: nkb (hi, lo) block pairs each, k-tile t at 2 t blocks
+    const char *ga = pa + (int64_t)tm * nkb * 2 * PK_BLOCK;
+    const char *gb = pb + (int64_t)tn * nkb * 2 * PK_BLOCK;
+
+    // k-tile t into stage s: 2 x 2048 chunks, chunk c * PX_NT + tid of each
+    // operand by this thread; a wave's 64 chunks of one load land contiguously
+    auto issue = [&](int t, int s) {
+        char *st = lds + s * PX_STAGE;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int ch = c * PX_NT + tid, wch = c * PX_NT + wave * 64;
+            __builtin_amdgcn_global_load_lds((const void *)(ga + (int64_t)t * 2 * PK_BLOCK + ch * 16),
+                                             (lds_void *)(st + wch * 16), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(gb + (int64_t)t * 2 * PK_BLOCK + ch * 16),
+                                             (lds_void *)(st + 2 * PK_BLOCK + wch * 16), 16, 0, 0);
+        }
+    };
+    // fragment of rows r0 .. r0+15 (this lane's row r0 + (lane & 15)), k = 8 (lane >> 4) .. +7
+    auto frag = [&](const char *plane, int r0) {
+        const int r = r0 + (lane & 15);
+        return *(const bf16x8 *)(plane + pk_chunk(r, lane >> 4) * 16);
+    };
+
+    v4f acc[PX_WMB][PX_WNB];
+#pragma unroll
+    for (int a = 0; a < PX_WMB; ++a)
+#pragma unroll
+        for (int b = 0; b < PX_WNB; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+
+    issue(0, 0);
+    if (nkb > 1) issue(1, 1);
+    for (int t = 0; t < nkb; ++t) {
+        if (t + 1 < nkb) asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+        else asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+        const char *st = lds + (t & 1) * PX_STAGE;
+        const char *ah_p = st, *al_p = st + PK_BLOCK, *bh_p = st + 2 * PK_BLOCK, *bl_p = st + 3 * PK_BLOCK;
+        bf16x8 ah[PX_WMB], al[PX_WMB];
+#pragma unroll
+        for (int a = 0; a < PX_WMB; ++a) {
+            ah[a] = frag(ah_p, wm0 + 16 * a);
+            al[a] = frag(al_p, wm0 + 16 * a);
+        }
+#pragma unroll
+        for (int b = 0; b < PX_WNB; ++b) {
+            const bf16x8 bh = frag(bh_p, wn0 + 16 * b), bl = frag(bl_p, wn0 + 16 * b);
+#pragma unroll
+            for (int a = 0; a < PX_WMB; ++a) {
+                acc[a][b] = mfma_bf16(bl, ah[a], acc[a][b]);
+                acc[a][b] = mfma_bf16(bh, al[a], acc[a][b]);
+                acc[a][b] = mfma_bf16(bh, ah[a], acc[a][b]);
+            }
+        }
+        // every wave's reads of this stage are done before it is refilled
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        if (t + 2 < nkb) issue(t + 2, t & 1);
+    }
+    constexpr int MODE_A = mode_of<CS, true>(), MODE_B = mode_of<CS, false>();
+    constexpr bool MDBL = MODE_A == M_MNINT || MODE_A == M_ONEE, NDBL = MODE_B == M_MNINT || MODE_B == M_ONEE;
+    x16_epilogue<CS, false, PX_WMB, PX_WNB>(g, acc, (int64_t)tm * (PK_ROWS / (MDBL ? 2 : 1)),
+                                            (int64_t)tn * (PK_ROWS / (NDBL ? 2 : 1)), wm0, wn0, lane);
+}
+
+}  // namespace md

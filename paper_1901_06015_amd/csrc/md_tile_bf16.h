@@ -108,6 +108,76 @@ __device__ __forceinline__ v4f mfma_f16(bf16x8 x, bf16x8 y, v4f c) {
                                                   0, 0);
 }
 
+// Epilogue of the 16-bit-product kernels: acc[a][b] item v is
+// C'(row m = wm0 + 16a + (lane & 15), col n = wn0 + 16b + acc_row(lane, v)) of
+// the workgroup tile whose first stored rows / columns are i0 / j0.  GS: C has
+// general strides.  Binary16 C takes the general update (decided once per
+// workgroup), so the common case keeps the plain update's code.  The general
+// update is too large to inline at every accumulator of the wide tiles: there
+// the loop over row blocks stays rolled and picks its accumulator with
+// selects (an indexed access would put the accumulators in scratch).
+template <int CS, bool GS, int WMB, int WNB>
+__device__ __forceinline__ void x16_epilogue(const GemmArgs &g, v4f (&acc)[WMB][WNB], int64_t i0, int64_t j0,
+                                             int wm0, int wn0, int lane) {
+    constexpr int MODE_A = mode_of<CS, true>(), MODE_B = mode_of<CS, false>();
+    constexpr bool MDBL = MODE_A == M_MNINT || MODE_A == M_ONEE;
+    constexpr bool NDBL = MODE_B == M_MNINT || MODE_B == M_ONEE;
+    constexpr bool CCPLX = (CS == MD_CASE_1C || CS == MD_CASE_2AC || CS == MD_CASE_2BC || CS == MD_CASE_3);
+    auto epilogue = [&](auto general_tag) {
+        constexpr bool GEN = decltype(general_tag)::value;
+        auto pick = [&](int a, int b, int v) {
+            float r = acc[0][b][v];
+#pragma unroll
+            for (int x = 1; x < WMB; ++x) r = (a == x) ? acc[x][b][v] : r;
+            return r;
+        };
+        // general updates per thread: rolled from 64 on
+        constexpr int NCALL = WNB * 4 * (MDBL ? WMB / 2 : WMB) / (NDBL ? 2 : 1);
+        constexpr bool ROLL = GEN && NCALL >= 64;
+        auto rows = [&](int count, auto fn) {
+            if constexpr (ROLL) {
+#pragma unroll 1
+                for (int a = 0; a < count; ++a) fn(a);
+            } else {
+#pragma unroll
+                for (int a = 0; a < count; ++a) fn(a);
+            }
+        };
+        const int ml = lane & 15;
+#pragma unroll
+        for (int b = 0; b < WNB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int nl = acc_row<float>(lane, v);
+                if constexpr (MDBL) {
+                    rows(WMB / 2, [&](int q) {
+                        const int64_t i = i0 + wm0 / 2 + q * 16 + ml;
+                        const int64_t j = j0 + wn0 + b * 16 + nl;
+                        update_cplx<float, GS, GEN>(g, i, j, pick(2 * q, b, v), pick(2 * q + 1, b, v));
+                    });
+                } else if constexpr (NDBL) {
+                    if ((b & 1) == 0) {
+                        rows(WMB, [&](int a) {
+                            const int64_t i = i0 + wm0 + a * 16 + ml;
+                            const int64_t j = j0 + wn0 / 2 + (b / 2) * 16 + nl;
+                            update_cplx<float, GS, GEN>(g, i, j, pick(a, b, v), pick(a, b + 1, v));
+                        });
+                    }
+                } else {
+                    rows(WMB, [&](int a) {
+                        const int64_t i = i0 + wm0 + a * 16 + ml;
+                        const int64_t j = j0 + wn0 + b * 16 + nl;
+                        if constexpr (CCPLX) update_cplx<float, GS, GEN>(g, i, j, pick(a, b, v), 0.0f);
+                        else update_real<float, GS, GEN>(g, i, j, pick(a, b, v));
+                    });
+                }
+            }
+        }
+    };
+    if (g.c_half) epilogue(std::true_type{});
+    else epilogue(std::false_type{});
+}
+
 template <int CS, bool FAST, bool AD, bool BD, bool AMNC, bool BMNC, class C = TileCfg<float>, bool RAG = false,
           bool SCL = false, bool H16 = false, bool SH = false>
 __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
@@ -118,8 +188,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     typedef LayBF<AMNC, C::BM> LA;
     typedef LayBF<BMNC, C::BN> LB;
     static_assert(SA::TK == SB::TK, "A and B disagree on the k lowering");
-    constexpr bool MDBL = SA::MN2, NDBL = SB::MN2;
-    constexpr bool CCPLX = (CS == MD_CASE_1C || CS == MD_CASE_2AC || CS == MD_CASE_2BC || CS == MD_CASE_3);
+    static_assert(SA::MN2 == (mode_of<CS, true>() == M_MNINT || mode_of<CS, true>() == M_ONEE), "m' doubling");
 
     // [buffer][plane hi/lo (one binary16 plane with H16)][...]
     constexpr int NPL = H16 ? 1 : 2;
@@ -200,64 +269,7 @@ __global__ __launch_bounds__(C::NT, C::OCC) void md_bf16x3_kernel(GemmArgs g) {
     }
     tile(t & 1, false, nk);
 
-    // Binary16 C takes the general update (decided once per workgroup), so
-    // the common case keeps the plain update's code.  The general update is
-    // too large to inline at every accumulator of the wide tiles: there the
-    // loop over row blocks stays rolled and picks its accumulator with
-    // selects (an indexed access would put the accumulators in scratch).
-    auto epilogue = [&](auto general_tag) {
-        constexpr bool GEN = decltype(general_tag)::value;
-        auto pick = [&](int a, int b, int v) {
-            float r = acc[0][b][v];
-#pragma unroll
-            for (int x = 1; x < WMB; ++x) r = (a == x) ? acc[x][b][v] : r;
-            return r;
-        };
-        // general updates per thread: rolled from 64 on
-        constexpr int NCALL = WNB * 4 * (MDBL ? WMB / 2 : WMB) / (NDBL ? 2 : 1);
-        constexpr bool ROLL = GEN && NCALL >= 64;
-        auto rows = [&](int count, auto fn) {
-            if constexpr (ROLL) {
-#pragma unroll 1
-                for (int a = 0; a < count; ++a) fn(a);
-            } else {
-#pragma unroll
-                for (int a = 0; a < count; ++a) fn(a);
-            }
-        };
-        const int ml = lane & 15;
-#pragma unroll
-        for (int b = 0; b < WNB; ++b) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int nl = acc_row<float>(lane, v);
-                if constexpr (MDBL) {
-                    rows(WMB / 2, [&](int q) {
-                        const int64_t i = (int64_t)tm * SA::TMN + wm0 / 2 + q * 16 + ml;
-                        const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                        update_cplx<float, !FAST, GEN>(g, i, j, pick(2 * q, b, v), pick(2 * q + 1, b, v));
-                    });
-                } else if constexpr (NDBL) {
-                    if ((b & 1) == 0) {
-                        rows(WMB, [&](int a) {
-                            const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
-                            const int64_t j = (int64_t)tn * SB::TMN + wn0 / 2 + (b / 2) * 16 + nl;
-                            update_cplx<float, !FAST, GEN>(g, i, j, pick(a, b, v), pick(a, b + 1, v));
-                        });
-                    }
-                } else {
-                    rows(WMB, [&](int a) {
-                        const int64_t i = (int64_t)tm * SA::TMN + wm0 + a * 16 + ml;
-                        const int64_t j = (int64_t)tn * SB::TMN + wn0 + b * 16 + nl;
-                        if constexpr (CCPLX) update_cplx<float, !FAST, GEN>(g, i, j, pick(a, b, v), 0.0f);
-                        else update_real<float, !FAST, GEN>(g, i, j, pick(a, b, v));
-                    });
-                }
-            }
-        }
-    };
-    if (g.c_half) epilogue(std::true_type{});
-    else epilogue(std::false_type{});
+    x16_epilogue<CS, !FAST, WMB, WNB>(g, acc, (int64_t)tm * SA::TMN, (int64_t)tn * SB::TMN, wm0, wn0, lane);
 }
 
 }  // namespace md

@@ -217,6 +217,21 @@ Decision decide(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
         tmn_a = SMALL_TILE / (L.mdbl ? 2 : 1);
         tmn_b = SMALL_TILE / (L.ndbl ? 2 : 1);
     }
+    // BF16x3 large enough to fill the GPU with 256 x 256 tiles: packed
+    // operands (BLAS or row-major storage, no binary16 operand, no operand
+    // staged with alpha)
+    const char *pk = getenv("MDGEMM_PACK");
+    const int pmode = pk ? atoi(pk) : 1;
+    if (d.prec == PREC_BF16X3 && pmode != 0 && rsa == 1 && rsb == 1 && plain_c && !g.a_half && !g.b_half &&
+        !a_scale && !b_scale) {
+        const int64_t pa = PACK_TILE / (L.mdbl ? 2 : 1), pb = PACK_TILE / (L.ndbl ? 2 : 1);
+        const int64_t ptiles = ((m + pa - 1) / pa) * ((n + pb - 1) / pb);
+        if (pmode == 2 || (ptiles >= PACK_MIN_TILES && k * (L.kdbl ? 2 : 1) >= 256)) {
+            g.packed = 1;
+            tmn_a = pa;
+            tmn_b = pb;
+        }
+    }
     g.tiles_m = (int)((m + tmn_a - 1) / tmn_a);
     g.tiles_n = (int)((n + tmn_b - 1) / tmn_b);
     return d;
@@ -325,6 +340,7 @@ int mdgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, md_sc
         int bm, bn, bk;
         tile_shape(d.prec, d.cs, d.g.a_vec && d.g.b_vec, &bm, &bn, &bk);
         if (d.g.small) bm = bn = SMALL_TILE, bk = 4;
+        if (d.g.packed) bm = bn = PACK_TILE, bk = 32;
         out->tile_m = bm; out->tile_n = bn; out->tile_k = bk;
         out->workgroups = (int64_t)d.g.tiles_m * d.g.tiles_n;
         kernel_name(d.prec, d.cs, d.g, out->kernel, (int)sizeof(out->kernel));

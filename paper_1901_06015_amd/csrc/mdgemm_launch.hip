@@ -213,6 +213,22 @@ int launch_gemm(int prec, int cs, const GemmArgs &a0, void *stream, int64_t *wg,
     if (a0.small) return launch_small(prec, cs, a0, stream);
     hipStream_t s = (hipStream_t)stream;
     GemmArgs a = a0;
+    if (a0.packed) {
+        // packing takes a workspace: only where the caller allows allocation
+        const int rc = may_split ? launch_packed(cs, a0, stream) : MD_ERR_BUDGET;
+        if (rc != MD_ERR_BUDGET) return rc;
+        // no workspace: the unpacked kernel on its own tiles
+        int bm, bn, bk;
+        tile_shape(prec, cs, a0.a_vec && a0.b_vec, &bm, &bn, &bk);
+        const Lowering L = lower_case(cs);
+        const int64_t tmn_a = bm / (L.mdbl ? 2 : 1), tmn_b = bn / (L.ndbl ? 2 : 1);
+        a.packed = 0;
+        a.tiles_m = (int)((a0.m + tmn_a - 1) / tmn_a);
+        a.tiles_n = (int)((a0.n + tmn_b - 1) / tmn_b);
+        if (wg) *wg = (int64_t)a.tiles_m * a.tiles_n;
+        enqueue_product(prec, cs, a, s, (int64_t)a.tiles_m * a.tiles_n);
+        return hipGetLastError() == hipSuccess ? 0 : MD_ERR_HIP;
+    }
     a.splits = may_split ? split_count(prec, cs, a0, n) : 1;
     a.part = nullptr;
     if (a.splits > 1) {
@@ -261,9 +277,9 @@ void kernel_name(int prec, int cs, const GemmArgs &a, char *out, int len) {
     snprintf(out, len, "md_gemm_%s_case%s_%s_%c%c_%s",
              prec == PREC_D ? "f64" : prec == PREC_S ? "f32" : prec == PREC_H ? "f16" : "bf16x3",
              (cs >= 0 && cs < 8) ? cases[cs] : "?",
-             a.small ? "small" : (a.a_vec && a.b_vec) ? ((a.a_ragged || a.b_ragged) ? "ragged" : "fast") : "generic",
+             a.small ? "small" : a.packed ? "packed" : (a.a_vec && a.b_vec) ? ((a.a_ragged || a.b_ragged) ? "ragged" : "fast") : "generic",
              a.a_dbl ? 'd' : (a.a_half ? 'h' : 's'), a.b_dbl ? 'd' : (a.b_half ? 'h' : 's'),
-             a.small ? "t32x32w8" : tiles[kind]);
+             a.small ? "t32x32w8" : a.packed ? "t256x256w8" : tiles[kind]);
 }
 
 }  // namespace md

@@ -373,3 +373,28 @@ def test_tune_table_file_round_trip_and_malformed_files(tmp_path):
         assert _lib.tune_get("d", "3", 4, 4) == _lib.GTILE_NAMES.index("64x64k")
     finally:
         _lib.tune_load(None)
+
+
+def test_bf16x3_packed_path_choice(monkeypatch):
+    """BF16x3 runs on packed operands from 128 tiles of 256 x 256 (and
+    k' >= 256) on; MDGEMM_PACK=0 turns it off, 2 forces it for any size; never
+    for general strides, binary16 operands or other precisions."""
+    def plan(m, n, k, tc="s", ta="s", tb="s", comp="bf16x3", lda=None):
+        st, pl = _lib.mdgemm_plan("N", "N", m, n, k, 1.0, 16, ta, lda or m, 16, tb, k, 1.0, 16, tc, m, comp)
+        assert st == 0
+        return pl
+    monkeypatch.delenv("MDGEMM_PACK", raising=False)
+    big = plan(4096, 2048, 512)                     # 16 x 8 = 128 tiles
+    assert "packed" in big["kernel"] and big["tile_m"] == 256 and big["tile_n"] == 256
+    assert big["workgroups"] == 16 * 8
+    assert "packed" not in plan(4096, 1792, 512)["kernel"]    # 112 tiles
+    assert "packed" not in plan(4096, 4096, 100)["kernel"]    # k' < 256
+    ccs = plan(4096, 4096, 256, "c", "c", "s")                # case 2ac: m' = 8192
+    assert "packed" in ccs["kernel"] and ccs["workgroups"] == 32 * 16
+    assert "packed" not in plan(8192, 8192, 8192, comp="s")["kernel"]
+    assert "packed" not in plan(8192, 8192, 8192, ta="h", tb="h", comp="bf16x3")["kernel"]
+    monkeypatch.setenv("MDGEMM_PACK", "0")
+    assert "packed" not in plan(8192, 8192, 8192)["kernel"]
+    monkeypatch.setenv("MDGEMM_PACK", "2")
+    small = plan(40, 30, 20)
+    assert "packed" in small["kernel"] and small["workgroups"] == 1

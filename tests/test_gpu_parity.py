@@ -237,6 +237,57 @@ def test_bf16x3_transposes_and_loguniform():
         one(cab[0], cab[1], cab[2], 128, 128, 256, "bf16x3", dist="loguniform", beta=0.0)
 
 
+# BF16x3 on packed operands (cast, split and packed once, then multiplied from
+# direct LDS copies): forced at every size with MDGEMM_PACK=2.
+@pytest.fixture
+def packed(monkeypatch):
+    monkeypatch.setenv("MDGEMM_PACK", "2")
+
+
+def _plan_kernel(tc, ta, tb, m, n, k, comp, transa="N", transb="N"):
+    ar = m if transa in "NR" else k
+    br = k if transb in "NR" else n
+    st, pl = _lib.mdgemm_plan(transa, transb, m, n, k, 1.5, 1, ta, ar, 1, tb, br, -0.5, 1, tc, m, comp)
+    assert st == 0
+    return pl["kernel"]
+
+
+@pytest.mark.parametrize("cab", ["sss", "css", "ccs", "ccc", "scs", "scc", "zdz", "dzd", "zzz", "czd", "sdc",
+                                 "dcc"])
+def test_bf16x3_packed_all_cases_and_ops(cab, packed):
+    """Every case, double- and single-stored operands, the op pairs, ragged m,
+    n and k (none a multiple of the 256 x 256 x 32 packed tile): within the
+    BF16x3 bound; ld padding of C untouched."""
+    tc, ta, tb = cab
+    for i, (transa, transb) in enumerate((("N", "N"), ("T", "N"), ("N", "C"), ("C", "T"), ("R", "N"))):
+        m, n, k = (300, 270, 77) if i % 2 == 0 else (97, 333, 130)
+        assert "packed" in _plan_kernel(tc, ta, tb, m, n, k, "bf16x3", transa, transb)
+        one(tc, ta, tb, m, n, k, "bf16x3", transa, transb, seed=31 + i)
+
+
+def test_bf16x3_packed_exact_inputs_bitwise(packed):
+    for tc, ta, tb in itertools.product("sc", "sdcz", "sdcz"):
+        say("bf16x3 packed exact %s%s%s" % (tc, ta, tb))
+        m, n, k = 260, 40, 70
+        st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp="bf16x3", dist="int", seed=17)
+        assert st == 0, st
+        ref, _ = gu.reference(tc, ta, tb, m, n, k, ops)
+        got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+        assert np.array_equal(got, ref), "packed exact %s%s%s: %d mismatches" % (tc, ta, tb, int((got != ref).sum()))
+
+
+def test_bf16x3_packed_beta_zero_and_half_c(packed):
+    """beta = 0 does not read C (NaN there stays out); a binary16 C takes the
+    general epilogue of the packed kernel."""
+    one("c", "c", "s", 270, 260, 64, "bf16x3", beta=0.0)
+    for tc in ("h", "hc"):
+        say("bf16x3 packed half C", tc)
+        st, Cout, ops = gu.run(tc, "s", "c" if tc == "hc" else "s", 140, 300, 96, comp="bf16x3", seed=5)
+        assert st == 0, st
+        ref, g = gu.reference(tc, "s", "c" if tc == "hc" else "s", 140, 300, 96, ops)
+        gu.check(tc, "bf16x3", 96, Cout, 140, 300, ref, g, what="packed half C %s" % tc)
+
+
 @pytest.mark.parametrize("layouts", list(itertools.product(("col", "row", "gen", "genr"), repeat=3)))
 def test_row_and_column_strides(layouts):
     """Section 3's row and column strides: every operand stored by columns, by
