@@ -29,44 +29,98 @@ constexpr int PK_BLOCK = PK_ROWS * PK_K * 2;   // bytes of one plane of one bloc
 // distinct groups of 4 LDS banks.
 __host__ __device__ constexpr int pk_chunk(int r, int q) { return 4 * r + (q ^ ((r >> 2) & 3)); }
 
-// One workgroup per packed block (blockIdx.x = rb * nkb + kb), one thread per
-// row: 32 elements of the real product's operand, cast to FP32 as the
-// staging of md_tile.h does (double -> float rounds to nearest even), split
-// and stored.  Elements outside the matrix are zero.  Threads of consecutive
-// rows read consecutive addresses of an operand stored along m' or n'.
-template <int CS, bool IS_A, bool SDBL>
-__global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *out, int nkb) {
+// One workgroup per packed block (blockIdx.x = rb * nkb + kb): 32 elements of
+// the real product's operand per row, cast to FP32 as the staging of
+// md_tile.h does (double -> float rounds to nearest even), split and stored;
+// elements outside the matrix are zero.  The threads follow the operand's
+// storage (MNC: stored along m' or n', as the operation makes it; chosen by
+// the host): for an operand stored along m' or n' one thread per row (lanes of
+// a load read consecutive rows: consecutive addresses); for one stored along
+// k four consecutive lanes take the four 8-element chunks of one row (a load
+// reads 16 rows of 32 consecutive elements, whole lines the next loads
+// reuse).  Each thread issues all 32 loads before converting (the output is
+// restrict, so no store holds a load back).
+template <int CS, bool IS_A, bool SDBL, bool MNC>
+__global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *__restrict__ out, int nkb) {
     typedef SmallOp<float, CS, IS_A, SDBL> Op;
     const Op op(g);
     const int rb = (int)(blockIdx.x / (unsigned)nkb), kb = (int)(blockIdx.x % (unsigned)nkb);
-    const int r = threadIdx.x;
-    const int64_t row = (int64_t)rb * PK_ROWS + r, k0 = (int64_t)kb * PK_K;
+    const int tid = threadIdx.x;
+    const int64_t k0 = (int64_t)kb * PK_K;
     char *hi = out + (int64_t)blockIdx.x * 2 * PK_BLOCK, *lo = hi + PK_BLOCK;
+    // this thread's four chunks: (block row, chunk index)
+    int cr[4], cq[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        bf16x8 h, l;
+    for (int c = 0; c < 4; ++c) {
+        cr[c] = MNC ? tid : c * (PK_ROWS / 4) + (tid >> 2);
+        cq[c] = MNC ? c : (tid & 3);
+    }
+    uint32_t wlo[4][8], whi[4][8];
+    uint32_t vmask = 0, nmask = 0;
+    // Stored along k, the plain and k-interleaved lowerings put the 8
+    // elements of a chunk in 8 consecutive stored words: a chunk wholly
+    // inside the matrix is read with 16-byte loads (same words).
+    constexpr bool KRUN = Op::MODE == M_PLAIN || Op::MODE == M_KINT;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int64_t off[8];
+        uint32_t cv = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             bool valid, neg;
-            uint32_t wlo, whi = 0;
-            op.issue(op.where(row, k0 + 8 * q + j, true, &valid, &neg), &wlo, &whi);
-            const float v = Op::value(wlo, whi, valid, neg);
+            off[j] = op.where((int64_t)rb * PK_ROWS + cr[c], k0 + 8 * cq[c] + j, true, &valid, &neg);
+            cv |= (uint32_t)valid << j;
+            nmask |= (uint32_t)neg << (8 * c + j);
+        }
+        vmask |= cv << (8 * c);
+        if (KRUN && !MNC && cv == 0xffu) {
+            const uint4 *q = (const uint4 *)(op.base + off[0]);
+            if constexpr (SDBL) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint4 x = q[v];
+                    wlo[c][2 * v] = x.x;
+                    whi[c][2 * v] = x.y;
+                    wlo[c][2 * v + 1] = x.z;
+                    whi[c][2 * v + 1] = x.w;
+                }
+            } else {
+                const uint4 x0 = q[0], x1 = q[1];
+                wlo[c][0] = x0.x; wlo[c][1] = x0.y; wlo[c][2] = x0.z; wlo[c][3] = x0.w;
+                wlo[c][4] = x1.x; wlo[c][5] = x1.y; wlo[c][6] = x1.z; wlo[c][7] = x1.w;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) whi[c][j] = 0;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                whi[c][j] = 0;
+                op.issue(off[j], &wlo[c][j], &whi[c][j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        bf16x8 h, l;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = 8 * c + j;
+            const float v = Op::value(wlo[c][j], whi[c][j], (vmask >> e) & 1, (nmask >> e) & 1);
             const __bf16 vh = (__bf16)v;
             h[j] = vh;
             l[j] = (__bf16)(v - (float)vh);
         }
-        *(bf16x8 *)(hi + pk_chunk(r, q) * 16) = h;
-        *(bf16x8 *)(lo + pk_chunk(r, q) * 16) = l;
+        *(bf16x8 *)(hi + pk_chunk(cr[c], cq[c]) * 16) = h;
+        *(bf16x8 *)(lo + pk_chunk(cr[c], cq[c]) * 16) = l;
     }
 }
 
-// The multiply kernel: one 256 x 256 tile of the real product per
-// workgroup, 8 waves of 64 (m') x 128 (n'), one 32-deep k-tile per LDS stage
-// (A' hi, A' lo, B' hi, B' lo: 64 KB), two stages.  Each thread copies 8
-// chunks of 16 bytes per k-tile with direct-to-LDS loads; a wave waits for
-// its own copies of tile t (those of tile t+1 stay in flight) and the
-// barrier makes everyone's visible.  The waits and barriers are written as
-// asm with a memory clobber so that no memory access moves across them.
+// MD_PX_TWO_BARRIERS: refill a stage two tiles ahead behind a second
+// barrier per k-tile instead of one tile ahead behind the first (build
+// option; measured against the default).
+#ifndef MD_PX_TWO_BARRIERS
+#define MD_PX_TWO_BARRIERS 0
+#endif
 constexpr int PX_WGM = 4, PX_WGN = 2;
 constexpr int PX_WMB = PK_ROWS / (16 * PX_WGM), PX_WNB = PK_ROWS / (16 * PX_WGN);  // 4 x 8 blocks per wave
 constexpr int PX_NT = 64 * PX_WGM * PX_WGN;
@@ -110,11 +164,23 @@ __global__ __launch_bounds__(PX_NT, 2) void md_packed_x3_kernel(GemmArgs g, cons
 #pragma unroll
         for (int b = 0; b < PX_WNB; ++b) acc[a][b] = v4f{0, 0, 0, 0};
 
+#if MD_PX_TWO_BARRIERS
     issue(0, 0);
     if (nkb > 1) issue(1, 1);
+#else
+    issue(0, 0);
+#endif
     for (int t = 0; t < nkb; ++t) {
+#if MD_PX_TWO_BARRIERS
         if (t + 1 < nkb) asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
         else asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+#else
+        // tile t has landed for every wave, and every wave has finished
+        // reading the other stage (tile t-1): refill it with tile t+1 at once,
+        // so the copies have this tile's MFMAs to arrive
+        asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+        if (t + 1 < nkb) issue(t + 1, (t + 1) & 1);
+#endif
         const char *st = lds + (t & 1) * PX_STAGE;
         const char *ah_p = st, *al_p = st + PK_BLOCK, *bh_p = st + 2 * PK_BLOCK, *bl_p = st + 3 * PK_BLOCK;
         bf16x8 ah[PX_WMB], al[PX_WMB];
@@ -133,9 +199,11 @@ __global__ __launch_bounds__(PX_NT, 2) void md_packed_x3_kernel(GemmArgs g, cons
                 acc[a][b] = mfma_bf16(bh, ah[a], acc[a][b]);
             }
         }
+#if MD_PX_TWO_BARRIERS
         // every wave's reads of this stage are done before it is refilled
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         if (t + 2 < nkb) issue(t + 2, t & 1);
+#endif
     }
     constexpr int MODE_A = mode_of<CS, true>(), MODE_B = mode_of<CS, false>();
     constexpr bool MDBL = MODE_A == M_MNINT || MODE_A == M_ONEE, NDBL = MODE_B == M_MNINT || MODE_B == M_ONEE;

@@ -35,13 +35,21 @@ static void *pack_workspace_locked(hipStream_t s, size_t bytes) {
     return p;
 }
 
+template <int CS, bool IS_A, bool SDBL>
+static void enqueue_pack(const GemmArgs &a, hipStream_t s, char *out, int nkb, unsigned grid) {
+    const int tr = IS_A ? a.ta : a.tb;
+    const bool mnc = IS_A ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2);
+    if (mnc) hipLaunchKernelGGL((md_pack_x3_kernel<CS, IS_A, SDBL, true>), dim3(grid), dim3(PK_ROWS), 0, s, a, out, nkb);
+    else hipLaunchKernelGGL((md_pack_x3_kernel<CS, IS_A, SDBL, false>), dim3(grid), dim3(PK_ROWS), 0, s, a, out, nkb);
+}
+
 template <int CS>
 static void enqueue_packed(const GemmArgs &a, hipStream_t s, char *pa, char *pb, int nkb) {
     const unsigned ga = (unsigned)((int64_t)a.tiles_m * nkb), gb = (unsigned)((int64_t)a.tiles_n * nkb);
-    if (a.a_dbl) hipLaunchKernelGGL((md_pack_x3_kernel<CS, true, true>), dim3(ga), dim3(PK_ROWS), 0, s, a, pa, nkb);
-    else hipLaunchKernelGGL((md_pack_x3_kernel<CS, true, false>), dim3(ga), dim3(PK_ROWS), 0, s, a, pa, nkb);
-    if (a.b_dbl) hipLaunchKernelGGL((md_pack_x3_kernel<CS, false, true>), dim3(gb), dim3(PK_ROWS), 0, s, a, pb, nkb);
-    else hipLaunchKernelGGL((md_pack_x3_kernel<CS, false, false>), dim3(gb), dim3(PK_ROWS), 0, s, a, pb, nkb);
+    if (a.a_dbl) enqueue_pack<CS, true, true>(a, s, pa, nkb, ga);
+    else enqueue_pack<CS, true, false>(a, s, pa, nkb, ga);
+    if (a.b_dbl) enqueue_pack<CS, false, true>(a, s, pb, nkb, gb);
+    else enqueue_pack<CS, false, false>(a, s, pb, nkb, gb);
     hipLaunchKernelGGL((md_packed_x3_kernel<CS>), dim3((unsigned)((int64_t)a.tiles_m * a.tiles_n)), dim3(PX_NT), 0,
                        s, a, (const char *)pa, (const char *)pb, nkb);
 }
