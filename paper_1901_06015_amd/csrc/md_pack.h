@@ -121,13 +121,22 @@ __global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *_
 #ifndef MD_PX_TWO_BARRIERS
 #define MD_PX_TWO_BARRIERS 0
 #endif
-constexpr int PX_WGM = 4, PX_WGN = 2;
-constexpr int PX_WMB = PK_ROWS / (16 * PX_WGM), PX_WNB = PK_ROWS / (16 * PX_WGN);  // 4 x 8 blocks per wave
+// MD_PX_WAVES=4: 4 waves of 128 x 128 (a third fewer LDS reads per flop,
+// accumulators in AGPRs, one wave per SIMD); build option, measured 0.93x
+// the default 8 waves of 64 x 128.
+#ifndef MD_PX_WAVES
+#define MD_PX_WAVES 8
+#endif
+constexpr int PX_WGM = MD_PX_WAVES == 4 ? 2 : 4, PX_WGN = 2;
+constexpr int PX_WMB = PK_ROWS / (16 * PX_WGM), PX_WNB = PK_ROWS / (16 * PX_WGN);  // blocks per wave
 constexpr int PX_NT = 64 * PX_WGM * PX_WGN;
+constexpr int PX_CPT = 2 * PK_BLOCK / 16 / PX_NT;  // 16-byte chunks per thread per operand and k-tile
+constexpr int PX_WAVES_PER_SIMD = PX_NT / 64 / 4;
+static_assert(!MD_PX_TWO_BARRIERS || PX_CPT == 4, "the two-barrier loop waits for 8 copies per thread");
 constexpr int PX_STAGE = 4 * PK_BLOCK;
 
 template <int CS>
-__global__ __launch_bounds__(PX_NT, 2) void md_packed_x3_kernel(GemmArgs g, const char *pa, const char *pb,
+__global__ __launch_bounds__(PX_NT, PX_WAVES_PER_SIMD) void md_packed_x3_kernel(GemmArgs g, const char *pa, const char *pb,
                                                                 int nkb) {
     typedef __attribute__((address_space(3))) void lds_void;
     __shared__ __attribute__((aligned(16))) char lds[2 * PX_STAGE];
@@ -144,7 +153,7 @@ __global__ __launch_bounds__(PX_NT, 2) void md_packed_x3_kernel(GemmArgs g, cons
     auto issue = [&](int t, int s) {
         char *st = lds + s * PX_STAGE;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < PX_CPT; ++c) {
             const int ch = c * PX_NT + tid, wch = c * PX_NT + wave * 64;
             __builtin_amdgcn_global_load_lds((const void *)(ga + (int64_t)t * 2 * PK_BLOCK + ch * 16),
                                              (lds_void *)(st + wch * 16), 16, 0, 0);

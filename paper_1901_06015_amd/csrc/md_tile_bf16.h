@@ -131,9 +131,10 @@ __device__ __forceinline__ void x16_epilogue(const GemmArgs &g, v4f (&acc)[WMB][
             for (int x = 1; x < WMB; ++x) r = (a == x) ? acc[x][b][v] : r;
             return r;
         };
-        // general updates per thread: rolled from 64 on
+        // updates per thread: the general one rolled from 64 on, the plain
+        // one from 256 on
         constexpr int NCALL = WNB * 4 * (MDBL ? WMB / 2 : WMB) / (NDBL ? 2 : 1);
-        constexpr bool ROLL = GEN && NCALL >= 64;
+        constexpr bool ROLL = (GEN && NCALL >= 64) || NCALL >= 256;
         auto rows = [&](int count, auto fn) {
             if constexpr (ROLL) {
 #pragma unroll 1
