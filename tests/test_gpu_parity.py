@@ -614,3 +614,55 @@ def test_small_kernel_exact_inputs_bitwise():
             ref, _ = gu.reference(tc, ta, tb, 70, 66, 300, ops)
             got = np.asarray(Cout[:70, :66], dtype=np.complex128)
             assert np.array_equal(got, ref), "small exact %s%s%s/%s" % (tc, ta, tb, comp)
+
+
+def test_two_threads_share_a_stream_split_and_packed(monkeypatch):
+    """Two host threads enqueue products on the same stream at once: split-k
+    products (few tiles, deep k) and packed BF16x3 products, shapes growing
+    so that the per-stream workspaces are reallocated while the other thread
+    is using them.  Every result must match the oracle."""
+    import threading
+    monkeypatch.setenv("MDGEMM_SMALL", "0")
+    monkeypatch.setenv("MDGEMM_PACK", "2")
+    stream = torch.cuda.current_stream().cuda_stream
+    jobs = [[], []]
+    for t in range(2):
+        for i in range(4):
+            if (i + t) % 2 == 0:
+                cab, comp, (m, n, k) = ("zcd" if t == 0 else "dzz"), "d", (130 + 40 * i, 120 + 30 * t, 2000 + 500 * i)
+            else:
+                cab, comp, (m, n, k) = ("ccs" if t == 0 else "sdc"), "bf16x3", (90 + 70 * i, 260 + 50 * t, 300 + 200 * i)
+            tc, ta, tb = cab
+            A = inputs.matrix(m, k, ta, 900 + 10 * i + t)
+            B = inputs.matrix(k, n, tb, 950 + 10 * i + t)
+            C = inputs.matrix(m, n, tc, 990 + 10 * i + t)
+            jobs[t].append(dict(cab=cab, comp=comp, m=m, n=n, k=k, A=A, B=B, C=C,
+                                dA=gu.to_device(A), dB=gu.to_device(B), dC=gu.to_device(C)))
+    torch.cuda.synchronize()
+    status = [[], []]
+
+    def worker(t):
+        for j in jobs[t]:
+            tc, ta, tb = j["cab"]
+            st = _lib.mdgemm("N", "N", j["m"], j["n"], j["k"], 1.5, j["dA"].data_ptr(), ta, j["A"].shape[0],
+                             j["dB"].data_ptr(), tb, j["B"].shape[0], -0.5, j["dC"].data_ptr(), tc, j["C"].shape[0],
+                             j["comp"], stream)
+            status[t].append(st)
+
+    say("two threads on one stream: split-k and packed products")
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    assert status == [[0] * 4, [0] * 4], status
+    for t in range(2):
+        for j in jobs[t]:
+            tc, ta, tb = j["cab"]
+            say("check %s comp=%s %dx%dx%d (thread %d)" % (j["cab"], j["comp"], j["m"], j["n"], j["k"], t))
+            plan = _plan_kernel(tc, ta, tb, j["m"], j["n"], j["k"], j["comp"])
+            assert ("packed" in plan) == (j["comp"] == "bf16x3"), plan
+            ref, g = gu.reference(tc, ta, tb, j["m"], j["n"], j["k"], dict(A=j["A"], B=j["B"], C=j["C"]))
+            gu.check(tc, j["comp"], j["k"], gu.to_host(j["dC"]), j["m"], j["n"], ref, g,
+                     what="threaded %s/%s" % (j["cab"], j["comp"]))
