@@ -36,7 +36,10 @@
  *     classes, blocks recycled once the batch that used them has completed),
  *     so admission does no device allocation in steady state.  Each output is
  *     either kept as an operand handle (keep_output = 1; read it with
- *     md_server_fetch) or recycled on completion.
+ *     md_server_fetch) or recycled on completion.  Large requests run on
+ *     mdgemm's kernels, so the per-stream split-k and BF16x3 packing
+ *     workspaces of mdgemm.h (allocated on first need, grown, kept) apply to
+ *     the server's streams too; they are outside budget_bytes.
  *
  * All functions return 0 or a positive MD_ERR_* code (mdgemm.h), or a
  * negative argument position for md_server_submit (mdgemm's numbering).
