@@ -29,7 +29,7 @@ constexpr int PK_BLOCK = PK_ROWS * PK_K * 2;   // bytes of one plane of one bloc
 // distinct groups of 4 LDS banks.
 __host__ __device__ constexpr int pk_chunk(int r, int q) { return 4 * r + (q ^ ((r >> 2) & 3)); }
 
-// One workgroup per packed block (blockIdx.x = rb * nkb + kb): 32 elements of
+// One workgroup per packed block (blk = rb * nkb + kb): 32 elements of
 // the real product's operand per row, cast to FP32 as the staging of
 // md_tile.h does (double -> float rounds to nearest even), split and stored;
 // elements outside the matrix are zero.  The threads follow the operand's
@@ -41,13 +41,13 @@ __host__ __device__ constexpr int pk_chunk(int r, int q) { return 4 * r + (q ^ (
 // reuse).  Each thread issues all 32 loads before converting (the output is
 // restrict, so no store holds a load back).
 template <int CS, bool IS_A, bool SDBL, bool MNC>
-__global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *__restrict__ out, int nkb) {
+__device__ __forceinline__ void pack_block(const GemmArgs &g, char *__restrict__ out, int nkb, unsigned blk) {
     typedef SmallOp<float, CS, IS_A, SDBL> Op;
     const Op op(g);
-    const int rb = (int)(blockIdx.x / (unsigned)nkb), kb = (int)(blockIdx.x % (unsigned)nkb);
+    const int rb = (int)(blk / (unsigned)nkb), kb = (int)(blk % (unsigned)nkb);
     const int tid = threadIdx.x;
     const int64_t k0 = (int64_t)kb * PK_K;
-    char *hi = out + (int64_t)blockIdx.x * 2 * PK_BLOCK, *lo = hi + PK_BLOCK;
+    char *hi = out + (int64_t)blk * 2 * PK_BLOCK, *lo = hi + PK_BLOCK;
     // this thread's four chunks: (block row, chunk index)
     int cr[4], cq[4];
 #pragma unroll
@@ -113,6 +113,15 @@ __global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *_
         *(bf16x8 *)(hi + pk_chunk(cr[c], cq[c]) * 16) = h;
         *(bf16x8 *)(lo + pk_chunk(cr[c], cq[c]) * 16) = l;
     }
+}
+
+// One launch packs both operands: blocks [0, na) are A' blocks, the rest B'
+// blocks (the two packs overlap instead of running one after the other).
+template <int CS, bool AD, bool AMNC, bool BD, bool BMNC>
+__global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *__restrict__ pa,
+                                                             char *__restrict__ pb, int nkb, unsigned na) {
+    if (blockIdx.x < na) pack_block<CS, true, AD, AMNC>(g, pa, nkb, blockIdx.x);
+    else pack_block<CS, false, BD, BMNC>(g, pb, nkb, blockIdx.x - na);
 }
 
 // MD_PX_TWO_BARRIERS: refill a stage two tiles ahead behind a second

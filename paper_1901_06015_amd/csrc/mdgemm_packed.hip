@@ -35,21 +35,34 @@ static void *pack_workspace_locked(hipStream_t s, size_t bytes) {
     return p;
 }
 
-template <int CS, bool IS_A, bool SDBL>
-static void enqueue_pack(const GemmArgs &a, hipStream_t s, char *out, int nkb, unsigned grid) {
-    const int tr = IS_A ? a.ta : a.tb;
-    const bool mnc = IS_A ? (tr == 0 || tr == 3) : (tr == 1 || tr == 2);
-    if (mnc) hipLaunchKernelGGL((md_pack_x3_kernel<CS, IS_A, SDBL, true>), dim3(grid), dim3(PK_ROWS), 0, s, a, out, nkb);
-    else hipLaunchKernelGGL((md_pack_x3_kernel<CS, IS_A, SDBL, false>), dim3(grid), dim3(PK_ROWS), 0, s, a, out, nkb);
+template <int CS, bool AD, bool AMNC, bool BD>
+static void enqueue_pack_b(const GemmArgs &a, hipStream_t s, char *pa, char *pb, int nkb, unsigned na, unsigned nb) {
+    const bool bmnc = a.tb == 1 || a.tb == 2;
+    if (bmnc)
+        hipLaunchKernelGGL((md_pack_x3_kernel<CS, AD, AMNC, BD, true>), dim3(na + nb), dim3(PK_ROWS), 0, s, a, pa, pb,
+                           nkb, na);
+    else
+        hipLaunchKernelGGL((md_pack_x3_kernel<CS, AD, AMNC, BD, false>), dim3(na + nb), dim3(PK_ROWS), 0, s, a, pa, pb,
+                           nkb, na);
+}
+
+template <int CS, bool AD, bool AMNC>
+static void enqueue_pack_a(const GemmArgs &a, hipStream_t s, char *pa, char *pb, int nkb, unsigned na, unsigned nb) {
+    if (a.b_dbl) enqueue_pack_b<CS, AD, AMNC, true>(a, s, pa, pb, nkb, na, nb);
+    else enqueue_pack_b<CS, AD, AMNC, false>(a, s, pa, pb, nkb, na, nb);
 }
 
 template <int CS>
 static void enqueue_packed(const GemmArgs &a, hipStream_t s, char *pa, char *pb, int nkb) {
-    const unsigned ga = (unsigned)((int64_t)a.tiles_m * nkb), gb = (unsigned)((int64_t)a.tiles_n * nkb);
-    if (a.a_dbl) enqueue_pack<CS, true, true>(a, s, pa, nkb, ga);
-    else enqueue_pack<CS, true, false>(a, s, pa, nkb, ga);
-    if (a.b_dbl) enqueue_pack<CS, false, true>(a, s, pb, nkb, gb);
-    else enqueue_pack<CS, false, false>(a, s, pb, nkb, gb);
+    const unsigned na = (unsigned)((int64_t)a.tiles_m * nkb), nb = (unsigned)((int64_t)a.tiles_n * nkb);
+    const bool amnc = a.ta == 0 || a.ta == 3;
+    if (a.a_dbl) {
+        if (amnc) enqueue_pack_a<CS, true, true>(a, s, pa, pb, nkb, na, nb);
+        else enqueue_pack_a<CS, true, false>(a, s, pa, pb, nkb, na, nb);
+    } else {
+        if (amnc) enqueue_pack_a<CS, false, true>(a, s, pa, pb, nkb, na, nb);
+        else enqueue_pack_a<CS, false, false>(a, s, pa, pb, nkb, na, nb);
+    }
     hipLaunchKernelGGL((md_packed_x3_kernel<CS>), dim3((unsigned)((int64_t)a.tiles_m * a.tiles_n)), dim3(PX_NT), 0,
                        s, a, (const char *)pa, (const char *)pb, nkb);
 }
@@ -60,8 +73,7 @@ int launch_packed(int cs, const GemmArgs &a, void *stream) {
     const int64_t kr = a.k * (lower_case(cs).kdbl ? 2 : 1);
     const int64_t nkb64 = (kr + PK_K - 1) / PK_K;
     const size_t blocks = (size_t)(a.tiles_m + a.tiles_n) * (size_t)nkb64;
-    if (nkb64 > 0x7fffffff || (int64_t)a.tiles_m * nkb64 > 0x7fffffff || (int64_t)a.tiles_n * nkb64 > 0x7fffffff)
-        return MD_ERR_BUDGET;
+    if (nkb64 > 0x7fffffff || (int64_t)(a.tiles_m + a.tiles_n) * nkb64 > 0x7fffffff) return MD_ERR_BUDGET;
     const size_t bytes = blocks * 2 * PK_BLOCK;
     if (bytes > PACK_MAX_BYTES) return MD_ERR_BUDGET;
     hipStream_t s = (hipStream_t)stream;
