@@ -136,12 +136,21 @@ __global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *_
 #ifndef MD_PX_WAVES
 #define MD_PX_WAVES 8
 #endif
+// MD_PX_PIPE=0: one barrier at the top of each k-tile, then its fragment
+// reads in the compiler's schedule (all of A and two B blocks before the
+// first MFMA, each later B block just before its MFMAs); build option,
+// measured against the default.
+#ifndef MD_PX_PIPE
+#define MD_PX_PIPE 1
+#endif
 constexpr int PX_WGM = MD_PX_WAVES == 4 ? 2 : 4, PX_WGN = 2;
 constexpr int PX_WMB = PK_ROWS / (16 * PX_WGM), PX_WNB = PK_ROWS / (16 * PX_WGN);  // blocks per wave
 constexpr int PX_NT = 64 * PX_WGM * PX_WGN;
 constexpr int PX_CPT = 2 * PK_BLOCK / 16 / PX_NT;  // 16-byte chunks per thread per operand and k-tile
 constexpr int PX_WAVES_PER_SIMD = PX_NT / 64 / 4;
 static_assert(!MD_PX_TWO_BARRIERS || PX_CPT == 4, "the two-barrier loop waits for 8 copies per thread");
+static_assert(!(MD_PX_TWO_BARRIERS && MD_PX_PIPE), "MD_PX_TWO_BARRIERS is a variant of the MD_PX_PIPE=0 loop");
+static_assert(!MD_PX_PIPE || PX_WNB % 2 == 0, "the last B block and the next tile's first share no register");
 constexpr int PX_STAGE = 4 * PK_BLOCK;
 
 template <int CS>
@@ -182,6 +191,75 @@ __global__ __launch_bounds__(PX_NT, PX_WAVES_PER_SIMD) void md_packed_x3_kernel(
 #pragma unroll
         for (int b = 0; b < PX_WNB; ++b) acc[a][b] = v4f{0, 0, 0, 0};
 
+#if MD_PX_PIPE
+    // Fragments are read one step ahead of their MFMAs: B block b+1 right
+    // after the first MFMA of block b, and the next k-tile's A and B block 0
+    // (into the other register set) right after the first MFMA of the last
+    // block.  The compiler's waits here are for every outstanding LDS read,
+    // so each group of reads is issued just after a wait and has the rest of
+    // a block (3 * PX_WMB - 1 MFMAs) to arrive.  The k loop is unrolled by 2
+    // so that the register set is known at compile time.
+    bf16x8 ah[2][PX_WMB], al[2][PX_WMB], bh[2], bl[2];
+    auto read_a = [&](const char *st, auto set_tag) {
+        constexpr int P = decltype(set_tag)::value;
+#pragma unroll
+        for (int a = 0; a < PX_WMB; ++a) {
+            ah[P][a] = frag(st, wm0 + 16 * a);
+            al[P][a] = frag(st + PK_BLOCK, wm0 + 16 * a);
+        }
+    };
+    auto read_b = [&](const char *st, int b, int q) {
+        bh[q] = frag(st + 2 * PK_BLOCK, wn0 + 16 * b);
+        bl[q] = frag(st + 3 * PK_BLOCK, wn0 + 16 * b);
+    };
+    // the three products of block (a, b), from product `from` on
+    auto mfma_b = [&](auto set_tag, int b, int a, int from = 0) {
+        constexpr int P = decltype(set_tag)::value;
+        if (from <= 0) acc[a][b] = mfma_bf16(bl[b & 1], ah[P][a], acc[a][b]);
+        if (from <= 1) acc[a][b] = mfma_bf16(bh[b & 1], al[P][a], acc[a][b]);
+        acc[a][b] = mfma_bf16(bh[b & 1], ah[P][a], acc[a][b]);
+    };
+    // k-tile t, held in stage P = t & 1 and register set P
+    auto ktile = [&](auto set_tag, int t) {
+        constexpr int P = decltype(set_tag)::value;
+        const char *st = lds + P * PX_STAGE, *nx = lds + (P ^ 1) * PX_STAGE;
+#pragma unroll
+        for (int b = 0; b < PX_WNB; ++b) {
+            // the first product of the block, then the reads
+            acc[0][b] = mfma_bf16(bl[b & 1], ah[P][0], acc[0][b]);
+            if (b + 1 < PX_WNB) {
+                read_b(st, b + 1, (b + 1) & 1);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            } else if (t + 1 < nkb) {
+                // every read of stage P is done (block b's B was waited for
+                // by the MFMA above) and tile t+1 has landed for every wave:
+                // refill stage P with tile t+2, read tile t+1's first
+                // fragments while this block multiplies
+                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+                if (t + 2 < nkb) issue(t + 2, P);
+                read_b(nx, 0, 0);
+                read_a(nx, std::integral_constant<int, P ^ 1>{});
+                __builtin_amdgcn_sched_group_barrier(0x100, 2 + 2 * PX_WMB, 0);
+            }
+            mfma_b(set_tag, b, 0, 1);
+#pragma unroll
+            for (int a = 1; a < PX_WMB; ++a) mfma_b(set_tag, b, a);
+            __builtin_amdgcn_sched_group_barrier(0x008, 3 * PX_WMB - 1, 0);
+            // keep the next block's MFMAs (and their wait) behind this one's
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    issue(0, 0);
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    if (nkb > 1) issue(1, 1);
+    read_b(lds, 0, 0);
+    read_a(lds, std::integral_constant<int, 0>{});
+    for (int t = 0; t < nkb; t += 2) {
+        ktile(std::integral_constant<int, 0>{}, t);
+        if (t + 1 < nkb) ktile(std::integral_constant<int, 1>{}, t + 1);
+    }
+#else
 #if MD_PX_TWO_BARRIERS
     issue(0, 0);
     if (nkb > 1) issue(1, 1);
@@ -223,6 +301,7 @@ __global__ __launch_bounds__(PX_NT, PX_WAVES_PER_SIMD) void md_packed_x3_kernel(
         if (t + 2 < nkb) issue(t + 2, t & 1);
 #endif
     }
+#endif
     constexpr int MODE_A = mode_of<CS, true>(), MODE_B = mode_of<CS, false>();
     constexpr bool MDBL = MODE_A == M_MNINT || MODE_A == M_ONEE, NDBL = MODE_B == M_MNINT || MODE_B == M_ONEE;
     x16_epilogue<CS, false, PX_WMB, PX_WNB>(g, acc, (int64_t)tm * (PK_ROWS / (MDBL ? 2 : 1)),
