@@ -16,6 +16,11 @@
 
 namespace md {
 
+// MD_PACK_FAST=0: every block through the general (range-checked,
+// element-wise) path; build option, measured against the default.
+#ifndef MD_PACK_FAST
+#define MD_PACK_FAST 1
+#endif
 constexpr int PK_ROWS = 256;                   // rows (m' or n') of a packed block
 constexpr int PK_K = 32;                       // k' of a packed block
 constexpr int PK_BLOCK = PK_ROWS * PK_K * 2;   // bytes of one plane of one block (16 KB)
@@ -29,6 +34,144 @@ constexpr int PK_BLOCK = PK_ROWS * PK_K * 2;   // bytes of one plane of one bloc
 // distinct groups of 4 LDS banks.
 __host__ __device__ constexpr int pk_chunk(int r, int q) { return 4 * r + (q ^ ((r >> 2) & 3)); }
 
+// Split the FP32 values of a thread's four chunks into bf16 hi and lo and
+// store both planes.
+__device__ __forceinline__ void pack_store(const float (&v)[4][8], const int (&cr)[4], const int (&cq)[4], char *hi,
+                                           char *lo) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        bf16x8 h, l;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const __bf16 vh = (__bf16)v[c][j];
+            h[j] = vh;
+            l[j] = (__bf16)(v[c][j] - (float)vh);
+        }
+        *(bf16x8 *)(hi + pk_chunk(cr[c], cq[c]) * 16) = h;
+        *(bf16x8 *)(lo + pk_chunk(cr[c], cq[c]) * 16) = l;
+    }
+}
+
+// A block wholly inside the matrix (the common case): no range checks, and
+// offsets within 2 GiB of the block's first stored element, so buffer loads
+// with 32-bit offsets.  Stored along k, a chunk's 8 elements are one run of
+// stored components (8 for the plain and k-interleaved lowerings, 16 taking
+// every other for the Re-only and m/n-interleaved ones) read with 16-byte
+// loads (4-byte alignment suffices); stored along m' or n', one load per
+// element as in the general path, its k offset in a scalar register.
+template <int CS, bool IS_A, bool SDBL, bool MNC>
+__device__ __forceinline__ void pack_inside(const SmallOp<float, CS, IS_A, SDBL> &op, int64_t r0, int64_t k0,
+                                            const int (&cr)[4], const int (&cq)[4], char *hi, char *lo) {
+    typedef SmallOp<float, CS, IS_A, SDBL> Op;
+    constexpr int ESZ = SDBL ? 8 : 4, W = Op::W, MODE = Op::MODE;
+    constexpr bool MN2 = Op::MN2, K2 = Op::K2;
+    // stored (column or row) index and part of real row r; stored k index of k'
+    auto row_of = [](int64_t r, int *qm) {
+        *qm = MN2 ? (int)((r >> 4) & 1) : 0;
+        return MN2 ? (((r >> 5) << 4) | (r & 15)) : r;
+    };
+    const int64_t i0 = MN2 ? ((r0 >> 5) << 4) : r0, p0 = K2 ? (k0 >> 1) : k0;
+    const char *base = op.base + (MNC ? (i0 + p0 * op.ld) : (p0 + i0 * op.ld)) * W * ESZ;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
+    float v[4][8];
+    if constexpr (!MNC) {
+        constexpr bool STRIDE2 = (W == 2 && !K2);
+        constexpr int NV = (STRIDE2 ? 16 : 8) * ESZ / 16;  // 16-byte loads per chunk
+        uint32_t w[4][4 * NV];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int qm;
+            const int64_t i = row_of(r0 + cr[c], &qm);
+            const int64_t kk0 = k0 + 8 * cq[c], pc = K2 ? (kk0 >> 1) : kk0;
+            const uint32_t off = (uint32_t)(((i - i0) * op.ld + (pc - p0)) * W * ESZ);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
+                w[c][4 * q] = x[0];
+                w[c][4 * q + 1] = x[1];
+                w[c][4 * q + 2] = x[2];
+                w[c][4 * q + 3] = x[3];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int qm;
+            const int64_t r = r0 + cr[c];
+            (void)row_of(r, &qm);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                // component of element j within the run: its position, or
+                // the pair partner for the 1e lowering's odd rows (Im first),
+                // or every other component (offset by the part for m/n pairs)
+                int e0, e1;
+                if constexpr (K2) {
+                    e0 = j;
+                    e1 = (MODE == M_ONEE) ? (j ^ 1) : j;
+                } else if constexpr (STRIDE2) {
+                    e0 = 2 * j;
+                    e1 = (MODE == M_MNINT) ? 2 * j + 1 : 2 * j;
+                } else {
+                    e0 = e1 = j;
+                }
+                // both candidates as registers before the select (a select
+                // of two array elements would become an indexed access and
+                // put the array in scratch)
+                constexpr bool SEL = (K2 && MODE == M_ONEE) || (STRIDE2 && MODE == M_MNINT);
+                uint32_t lo_w, hi_w = 0;
+                if constexpr (!SEL) {
+                    lo_w = w[c][SDBL ? 2 * e0 : e0];
+                    if constexpr (SDBL) hi_w = w[c][2 * e0 + 1];
+                } else if constexpr (SDBL) {
+                    uint32_t a0 = w[c][2 * e0], a1 = w[c][2 * e0 + 1], b0 = w[c][2 * e1], b1 = w[c][2 * e1 + 1];
+                    asm("" : "+v"(a0), "+v"(a1), "+v"(b0), "+v"(b1));
+                    lo_w = qm ? b0 : a0;
+                    hi_w = qm ? b1 : a1;
+                } else {
+                    uint32_t a0 = w[c][e0], b0 = w[c][e1];
+                    asm("" : "+v"(a0), "+v"(b0));
+                    lo_w = qm ? b0 : a0;
+                }
+                bool valid, neg;
+                (void)op.where(r, k0 + 8 * cq[c] + j, true, &valid, &neg);
+                v[c][j] = Op::value(lo_w, hi_w, true, neg);
+            }
+        }
+    } else {
+        uint32_t wl[4][8], wh[4][8];
+        int qm;
+        const int64_t i = row_of(r0 + cr[0], &qm);
+        const uint32_t lane_off = (uint32_t)((i - i0) * W * ESZ);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t kk = k0 + 8 * cq[c] + j, p = K2 ? (kk >> 1) : kk;
+                const int qk = K2 ? (int)(kk & 1) : 0;
+                const int comp = MODE == M_KINT ? qk : MODE == M_MNINT ? qm : MODE == M_ONEE ? (qm ^ qk) : 0;
+                const int koff = (int)((p - p0) * op.ld * W * ESZ);
+                const uint32_t off = lane_off + (uint32_t)(comp * ESZ);
+                if constexpr (SDBL) {
+                    const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, koff, 0);
+                    wl[c][j] = x[0];
+                    wh[c][j] = x[1];
+                } else {
+                    wl[c][j] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, koff, 0);
+                    wh[c][j] = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                bool valid, neg;
+                (void)op.where(r0 + cr[c], k0 + 8 * cq[c] + j, true, &valid, &neg);
+                v[c][j] = Op::value(wl[c][j], wh[c][j], true, neg);
+            }
+    }
+    pack_store(v, cr, cq, hi, lo);
+}
+
 // One workgroup per packed block (blk = rb * nkb + kb): 32 elements of
 // the real product's operand per row, cast to FP32 as the staging of
 // md_tile.h does (double -> float rounds to nearest even), split and stored;
@@ -39,7 +182,8 @@ __host__ __device__ constexpr int pk_chunk(int r, int q) { return 4 * r + (q ^ (
 // k four consecutive lanes take the four 8-element chunks of one row (a load
 // reads 16 rows of 32 consecutive elements, whole lines the next loads
 // reuse).  Each thread issues all 32 loads before converting (the output is
-// restrict, so no store holds a load back).
+// restrict, so no store holds a load back).  Blocks wholly inside the matrix
+// take pack_inside.
 template <int CS, bool IS_A, bool SDBL, bool MNC>
 __device__ __forceinline__ void pack_block(const GemmArgs &g, char *__restrict__ out, int nkb, unsigned blk) {
     typedef SmallOp<float, CS, IS_A, SDBL> Op;
@@ -54,6 +198,21 @@ __device__ __forceinline__ void pack_block(const GemmArgs &g, char *__restrict__
     for (int c = 0; c < 4; ++c) {
         cr[c] = MNC ? tid : c * (PK_ROWS / 4) + (tid >> 2);
         cq[c] = MNC ? c : (tid & 3);
+    }
+    {
+        // the block's last stored row (or column) and k, and the byte span
+        // of its stored elements from the first: inside the matrix and
+        // within 2 GiB, take the fast path (uniform across the workgroup)
+        const int64_t r0 = (int64_t)rb * PK_ROWS, rl = r0 + PK_ROWS - 1;
+        const int64_t il = Op::MN2 ? (((rl >> 5) << 4) | 15) : rl;
+        const int64_t pl = Op::K2 ? ((k0 + PK_K - 1) >> 1) : (k0 + PK_K - 1);
+        const int64_t irange = il - (Op::MN2 ? ((r0 >> 5) << 4) : r0), prange = pl - (Op::K2 ? (k0 >> 1) : k0);
+        const int64_t span = ((MNC ? (irange + prange * op.ld) : (prange + irange * op.ld)) * Op::W + 2) *
+                             (SDBL ? 8 : 4);
+        if (MD_PACK_FAST && il < op.MN && pl < op.K && op.mnc == MNC && span < 0x7fff0000LL) {
+            pack_inside<CS, IS_A, SDBL, MNC>(op, r0, k0, cr, cq, hi, lo);
+            return;
+        }
     }
     uint32_t wlo[4][8], whi[4][8];
     uint32_t vmask = 0, nmask = 0;
@@ -99,20 +258,15 @@ __device__ __forceinline__ void pack_block(const GemmArgs &g, char *__restrict__
             }
         }
     }
+    float v[4][8];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        bf16x8 h, l;
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int e = 8 * c + j;
-            const float v = Op::value(wlo[c][j], whi[c][j], (vmask >> e) & 1, (nmask >> e) & 1);
-            const __bf16 vh = (__bf16)v;
-            h[j] = vh;
-            l[j] = (__bf16)(v - (float)vh);
+            v[c][j] = Op::value(wlo[c][j], whi[c][j], (vmask >> e) & 1, (nmask >> e) & 1);
         }
-        *(bf16x8 *)(hi + pk_chunk(cr[c], cq[c]) * 16) = h;
-        *(bf16x8 *)(lo + pk_chunk(cr[c], cq[c]) * 16) = l;
-    }
+    pack_store(v, cr, cq, hi, lo);
 }
 
 // One launch packs both operands: blocks [0, na) are A' blocks, the rest B'
