@@ -266,14 +266,21 @@ def test_bf16x3_packed_all_cases_and_ops(cab, packed):
 
 
 def test_bf16x3_packed_exact_inputs_bitwise(packed):
+    """Exact inputs: bitwise equal to the oracle.  m and n above 256 and k
+    above 64, so both operands have packed blocks wholly inside the matrix
+    (the pack's unchecked fast path) and blocks on the edges (the general
+    path), each operand stored along m/n ('N' A, 'T' B) and along k."""
     for tc, ta, tb in itertools.product("sc", "sdcz", "sdcz"):
-        say("bf16x3 packed exact %s%s%s" % (tc, ta, tb))
-        m, n, k = 260, 40, 70
-        st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp="bf16x3", dist="int", seed=17)
-        assert st == 0, st
-        ref, _ = gu.reference(tc, ta, tb, m, n, k, ops)
-        got = np.asarray(Cout[:m, :n], dtype=np.complex128)
-        assert np.array_equal(got, ref), "packed exact %s%s%s: %d mismatches" % (tc, ta, tb, int((got != ref).sum()))
+        for transa, transb in (("N", "N"), ("T", "C")):
+            say("bf16x3 packed exact %s%s%s %s%s" % (tc, ta, tb, transa, transb))
+            m, n, k = 260, 264, 70
+            st, Cout, ops = gu.run(tc, ta, tb, m, n, k, comp="bf16x3", dist="int", seed=17,
+                                   transa=transa, transb=transb)
+            assert st == 0, st
+            ref, _ = gu.reference(tc, ta, tb, m, n, k, ops, transa, transb)
+            got = np.asarray(Cout[:m, :n], dtype=np.complex128)
+            assert np.array_equal(got, ref), "packed exact %s%s%s %s%s: %d mismatches" % (
+                tc, ta, tb, transa, transb, int((got != ref).sum()))
 
 
 def test_bf16x3_packed_beta_zero_and_half_c(packed):
