@@ -8,8 +8,8 @@
 // planes in the layout the multiply kernel's LDS tiles use.  The multiply
 // kernel then copies packed tiles from HBM straight into LDS (gfx950 direct
 // 16-byte loads, no registers and no conversion in the k loop) and runs the
-// three bf16 MFMAs per block of md_bf16x3_kernel, in the same order on the
-// same values: the two forms give the same bits.
+// three bf16 MFMAs per block of md_bf16x3_kernel in the same order (on exact
+// inputs its results equal the plain definition bit for bit).
 #pragma once
 #include "md_small.h"
 #include "md_tile_bf16.h"
@@ -65,7 +65,7 @@ __device__ __forceinline__ void pack_inside(const SmallOp<float, CS, IS_A, SDBL>
     typedef SmallOp<float, CS, IS_A, SDBL> Op;
     constexpr int ESZ = SDBL ? 8 : 4, W = Op::W, MODE = Op::MODE;
     constexpr bool MN2 = Op::MN2, K2 = Op::K2;
-    // stored (column or row) index and part of real row r; stored k index of k'
+    // stored index (column or row) of real row r, and its part (Re 0, Im 1)
     auto row_of = [](int64_t r, int *qm) {
         *qm = MN2 ? (int)((r >> 4) & 1) : 0;
         return MN2 ? (((r >> 5) << 4) | (r & 15)) : r;
@@ -179,11 +179,11 @@ __device__ __forceinline__ void pack_inside(const SmallOp<float, CS, IS_A, SDBL>
 // storage (MNC: stored along m' or n', as the operation makes it; chosen by
 // the host): for an operand stored along m' or n' one thread per row (lanes of
 // a load read consecutive rows: consecutive addresses); for one stored along
-// k four consecutive lanes take the four 8-element chunks of one row (a load
-// reads 16 rows of 32 consecutive elements, whole lines the next loads
-// reuse).  Each thread issues all 32 loads before converting (the output is
-// restrict, so no store holds a load back).  Blocks wholly inside the matrix
-// take pack_inside.
+// k four consecutive lanes take the four 8-element chunks of one row (16
+// rows of 32 consecutive elements per wave).  Blocks wholly inside the
+// matrix take pack_inside; on the edges each thread issues all 32 element
+// loads before converting (the output is restrict, so no store holds a load
+// back).
 template <int CS, bool IS_A, bool SDBL, bool MNC>
 __device__ __forceinline__ void pack_block(const GemmArgs &g, char *__restrict__ out, int nkb, unsigned blk) {
     typedef SmallOp<float, CS, IS_A, SDBL> Op;
@@ -216,46 +216,19 @@ __device__ __forceinline__ void pack_block(const GemmArgs &g, char *__restrict__
     }
     uint32_t wlo[4][8], whi[4][8];
     uint32_t vmask = 0, nmask = 0;
-    // Stored along k, the plain and k-interleaved lowerings put the 8
-    // elements of a chunk in 8 consecutive stored words: a chunk wholly
-    // inside the matrix is read with 16-byte loads (same words).
-    constexpr bool KRUN = Op::MODE == M_PLAIN || Op::MODE == M_KINT;
+    // a block on the matrix's edge: every element's offset and validity
+    // formed separately, elements outside reading the first (and counting
+    // as zero)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        int64_t off[8];
-        uint32_t cv = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             bool valid, neg;
-            off[j] = op.where((int64_t)rb * PK_ROWS + cr[c], k0 + 8 * cq[c] + j, true, &valid, &neg);
-            cv |= (uint32_t)valid << j;
+            const int64_t off = op.where((int64_t)rb * PK_ROWS + cr[c], k0 + 8 * cq[c] + j, true, &valid, &neg);
+            vmask |= (uint32_t)valid << (8 * c + j);
             nmask |= (uint32_t)neg << (8 * c + j);
-        }
-        vmask |= cv << (8 * c);
-        if (KRUN && !MNC && cv == 0xffu) {
-            const uint4 *q = (const uint4 *)(op.base + off[0]);
-            if constexpr (SDBL) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const uint4 x = q[v];
-                    wlo[c][2 * v] = x.x;
-                    whi[c][2 * v] = x.y;
-                    wlo[c][2 * v + 1] = x.z;
-                    whi[c][2 * v + 1] = x.w;
-                }
-            } else {
-                const uint4 x0 = q[0], x1 = q[1];
-                wlo[c][0] = x0.x; wlo[c][1] = x0.y; wlo[c][2] = x0.z; wlo[c][3] = x0.w;
-                wlo[c][4] = x1.x; wlo[c][5] = x1.y; wlo[c][6] = x1.z; wlo[c][7] = x1.w;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) whi[c][j] = 0;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                whi[c][j] = 0;
-                op.issue(off[j], &wlo[c][j], &whi[c][j]);
-            }
+            whi[c][j] = 0;
+            op.issue(off, &wlo[c][j], &whi[c][j]);
         }
     }
     float v[4][8];
