@@ -259,7 +259,8 @@ __global__ __launch_bounds__(PK_ROWS) void md_pack_x3_kernel(GemmArgs g, char *_
 #endif
 // MD_PX_WAVES=4: 4 waves of 128 x 128 (a third fewer LDS reads per flop,
 // accumulators in AGPRs, one wave per SIMD); build option, measured 0.93x
-// the default 8 waves of 64 x 128.
+// the default 8 waves of 64 x 128 with MD_PX_PIPE=0 (with the default
+// MD_PX_PIPE its two register sets of A fragments do not fit and spill).
 #ifndef MD_PX_WAVES
 #define MD_PX_WAVES 8
 #endif
